@@ -1,0 +1,292 @@
+"""Pins of the oracle's whole RK2 step against what the physics fixes.
+
+- Sod's tube (the paper's Riemann problem is its 3D extension, Section 4)
+  against the exact solution, aligned with each axis;
+- a uniform state stays bitwise uniform (every face sees identical inputs);
+- periodic meshes conserve mass, momentum and energy to round-off;
+- with outflow walls the total x-momentum grows at exactly (p_L - p_R) times
+  the wall area while the waves are away from the walls;
+- the diagonal 32^3 problem is symmetric under permutations of the axes;
+- a density wave advected at uniform v, p keeps v and p uniform (a discrete
+  invariant of HLL on a contact) and converges at second order in L1;
+- the windowed step reproduces the full step bit for bit;
+- clipping the last step reaches the end time exactly;
+- the ghost layers follow the boundary definitions, and at an outflow wall
+  the flux is the edge cell's own physical flux.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from oracle.exact_riemann import RiemannSolution
+
+G = wl.GAMMA
+
+
+def _line(U, axis):
+    """The line of density along `axis` through transverse cell 0."""
+    rho = U[0]
+    if axis == 0:
+        return rho[0, 0, :]
+    if axis == 1:
+        return rho[0, :, 0]
+    return rho[:, 0, 0]
+
+
+def _sod_run(n, axis, t_end=0.25, transverse=2):
+    U = wl.sod(n, axis, transverse)
+    nz, ny, nx = U.shape[1:]
+    dts = oracle.run(U, wl.spacing(nx, ny, nz), G, 0.5, oracle.OUTFLOW, 100000, t_end)
+    return U, dts
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_sod_converges_to_exact_solution(axis):
+    sol = RiemannSolution(wl.SOD_LEFT, wl.SOD_RIGHT, G)
+    errs = []
+    for n in (64, 128, 256):
+        U, dts = _sod_run(n, axis)
+        assert math.fsum(dts) == pytest.approx(0.25, abs=1e-15)
+        exact = sol.cell_averages(np.arange(n + 1) / n, 0.25)
+        errs.append(np.mean(np.abs(_line(U, axis) - exact)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    # discontinuous solution: first order at best; require >= 0.5
+    assert min(orders) >= 0.5, (errs, orders)
+    assert errs[-1] < 4e-3
+
+
+def test_sod_wave_positions():
+    n = 256
+    U, _ = _sod_run(n, 0)
+    sol = RiemannSolution(wl.SOD_LEFT, wl.SOD_RIGHT, G)
+    x = (np.arange(n) + 0.5) / n
+    rho = U[0, 0, 0, :]
+    # shock: first cell from the right whose density exceeds the midpoint of
+    # the jump rho*_R -> rho_R
+    shock = 0.5 + sol.right_wave()[0] * 0.25
+    mid = 0.5 * (sol.rho_starR + 0.125)
+    i = np.max(np.nonzero(rho > mid)[0])
+    assert abs(x[i] - shock) < 3.0 / n
+    # contact: midpoint of rho*_L -> rho*_R
+    contact = 0.5 + sol.u_star * 0.25
+    midc = 0.5 * (sol.rho_starL + sol.rho_starR)
+    j = np.max(np.nonzero(rho > midc)[0])
+    assert abs(x[j] - contact) < 4.0 / n
+
+
+def test_sod_axes_agree_after_transposition():
+    n = 64
+    Ux, _ = _sod_run(n, 0, 0.1)
+    Uy, _ = _sod_run(n, 1, 0.1)
+    Uz, _ = _sod_run(n, 2, 0.1)
+    # x-aligned (nz=2, ny=2, nx=n) vs y-aligned (2, n, 2) vs z-aligned (n, 2, 2)
+    ry = np.transpose(Uy[0], (0, 2, 1))
+    rz = np.transpose(Uz[0], (2, 1, 0))
+    np.testing.assert_allclose(ry, Ux[0], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(rz, Ux[0], rtol=1e-13, atol=0)
+    # normal momentum moves with the axis
+    np.testing.assert_allclose(np.transpose(Uy[2], (0, 2, 1)), Ux[1], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(np.transpose(Uz[3], (2, 1, 0)), Ux[1], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("bc", [oracle.OUTFLOW, oracle.PERIODIC])
+def test_uniform_state_stays_bitwise_uniform(bc):
+    U = wl.uniform(5, 4, 3, rho=0.7, v=(0.3, -1.1, 0.25), p=2.5)
+    U0 = U.copy()
+    oracle.run(U, wl.spacing(5, 4, 3), G, 0.5, bc, 7)
+    assert np.array_equal(U, U0)
+
+
+def test_periodic_conservation():
+    n = (20, 16, 12)
+    U = wl.random_plane(*n, seed=3)
+    U[1] += 0.3 * U[0]            # add a bulk flow so momentum fluxes matter
+    U[4] += 0.5 * 0.09 * U[0]
+    before = [math.fsum(U[f].ravel()) for f in range(5)]
+    oracle.run(U, wl.spacing(*n), G, 0.5, oracle.PERIODIC, 12)
+    after = [math.fsum(U[f].ravel()) for f in range(5)]
+    scale = max(abs(b) for b in before)
+    for f in range(5):
+        assert abs(after[f] - before[f]) <= 1e-13 * scale, (f, before[f], after[f])
+
+
+def test_outflow_momentum_rate_equals_wall_pressure_difference():
+    n, tr = 128, 2
+    U = wl.sod(n, 0, tr)
+    h = 1.0 / n
+    dV = h ** 3
+    area = (tr * h) ** 2
+    mass0 = math.fsum(U[0].ravel()) * dV
+    en0 = math.fsum(U[4].ravel()) * dV
+    t_end = 0.2
+    dts = oracle.run(U, wl.spacing(n, tr, tr), G, 0.5, oracle.OUTFLOW, 100000, t_end)
+    t = math.fsum(dts)
+    assert t == pytest.approx(t_end, abs=1e-15)
+    mom = math.fsum(U[1].ravel()) * dV
+    assert mom == pytest.approx((1.0 - 0.1) * area * t, abs=1e-13 * area)
+    assert math.fsum(U[0].ravel()) * dV == pytest.approx(mass0, abs=1e-13 * mass0)
+    assert math.fsum(U[4].ravel()) * dV == pytest.approx(en0, abs=1e-13 * en0)
+    # transverse momenta stay exactly zero: transverse faces see equal states
+    assert not np.any(U[2]) and not np.any(U[3])
+
+
+def test_diagonal_problem_is_axis_permutation_symmetric():
+    U = wl.diagonal_riemann(32)
+    dts = oracle.run(U, wl.spacing(32, 32, 32), G, 0.5, oracle.OUTFLOW, 20)
+    assert len(dts) == 20
+    scale = np.max(np.abs(U), axis=(1, 2, 3))
+    # array axes are (z, y, x); a permutation of space permutes them and the
+    # momentum components together
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    for p in perms:   # p maps new spatial axis d -> old spatial axis p[d] (x=0)
+        arr_axes = tuple(2 - p[2 - a] for a in range(3))
+        V = np.empty_like(U)
+        V[0] = np.transpose(U[0], arr_axes)
+        V[4] = np.transpose(U[4], arr_axes)
+        for d in range(3):
+            V[1 + d] = np.transpose(U[1 + p[d]], arr_axes)
+        for f in range(5):
+            err = np.max(np.abs(V[f] - U[f])) / scale[f]
+            assert err < 1e-13, (p, f, err)
+
+
+def test_sine_wave_keeps_velocity_and_pressure_uniform():
+    n = 16
+    U = wl.sine_wave(n, n, n)
+    oracle.run(U, wl.spacing(n, n, n), G, 0.5, oracle.PERIODIC, 10)
+    v = U[1:4] / U[0]
+    p = (G - 1.0) * (U[4] - 0.5 * np.sum(U[1:4] * v, axis=0))
+    assert np.max(np.abs(v - 1.0)) < 1e-13
+    assert np.max(np.abs(p - 1.0)) < 1e-13
+
+
+def test_sine_wave_second_order_l1_convergence_1d():
+    errs = []
+    t_end = 0.25
+    for n in (128, 256, 512):
+        U = wl.sine_wave(n, 1, 1, k=(1, 0, 0), v=(1.0, 0.0, 0.0))
+        oracle.run(U, wl.spacing(n, 1, 1), G, 0.5, oracle.PERIODIC, 10 ** 6, t_end)
+        exact = wl.sine_density(n, 1, 1, k=(1, 0, 0), v=(1.0, 0.0, 0.0), t=t_end)
+        errs.append(np.mean(np.abs(U[0] - exact)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] >= 1.7, (errs, orders)
+    assert orders[-1] >= orders[0] - 0.05      # trending to 2, not away
+
+
+def test_sine_wave_l1_convergence_3d():
+    errs = []
+    t_end = 0.05
+    for n in (16, 32, 48):
+        U = wl.sine_wave(n, n, n)
+        oracle.run(U, wl.spacing(n, n, n), G, 0.5, oracle.PERIODIC, 10 ** 6, t_end)
+        errs.append(np.mean(np.abs(U[0] - wl.sine_density(n, n, n, t=t_end))))
+    order = math.log(errs[1] / errs[2]) / math.log(48 / 32)
+    assert order >= 1.5, (errs, order)
+
+
+@pytest.mark.parametrize("origin,size", [((0, 0, 0), (4, 3, 5)),
+                                         ((14, 9, 1), (6, 7, 4)),
+                                         ((-3, 5, 9), (3, 3, 3))])
+def test_window_step_equals_full_step(origin, size):
+    n = (16, 12, 10)
+    U = wl.random_plane(*n, seed=5)
+    sp = wl.spacing(*n)
+    dt = oracle.time_step(U, sp, G, 0.5)
+    full = U.copy()
+    oracle.step(full, sp, G, oracle.PERIODIC, dt)
+    win = oracle.step_window(U, sp, G, dt, origin, size)
+    ii = [(origin[0] + i) % n[0] for i in range(size[0])]
+    jj = [(origin[1] + j) % n[1] for j in range(size[1])]
+    kk = [(origin[2] + k) % n[2] for k in range(size[2])]
+    ref = full[:, kk][:, :, jj][:, :, :, ii]
+    assert np.array_equal(win, ref)
+
+
+def test_run_with_given_steps_matches_step():
+    n = (10, 9, 8)
+    U = wl.random_plane(*n, seed=9)
+    sp = wl.spacing(*n)
+    A = U.copy()
+    dts = oracle.run(A, sp, G, 0.5, oracle.OUTFLOW, 3)
+    B = U.copy()
+    for dt in dts:
+        assert dt == oracle.time_step(B, sp, G, 0.5)
+        oracle.step(B, sp, G, oracle.OUTFLOW, dt)
+    assert np.array_equal(A, B)
+
+
+def test_time_step_closed_form():
+    # uniform rho = 1, p = 1 at rest, gamma 1.4: c = sqrt(1.4), rate =
+    # 3 c / h, dt = CFL h / (3 c)
+    n = 8
+    U = wl.uniform(n, n, n)
+    dt = oracle.time_step(U, wl.spacing(n, n, n), G, 0.5)
+    assert dt == pytest.approx(0.5 / (3.0 * math.sqrt(1.4) * n), rel=1e-15)
+    # with velocity (1, -2, 0.5): rate = (1 + 2 + 0.5 + 3c)/h
+    U = wl.uniform(n, n, n, v=(1.0, -2.0, 0.5))
+    dt = oracle.time_step(U, wl.spacing(n, n, n), G, 0.5)
+    assert dt == pytest.approx(0.5 / ((3.5 + 3.0 * math.sqrt(1.4)) * n), rel=1e-15)
+
+
+@pytest.mark.parametrize("bc", [oracle.OUTFLOW, oracle.PERIODIC])
+def test_ghost_layers_follow_boundary_definition(bc):
+    # outflow: both ghost layers repeat the edge proper cell; periodic: the
+    # ghosts are the proper cells from the opposite side (-2 <- n-2,
+    # -1 <- n-1, n <- 0, n+1 <- 1).
+    nx, ny, nz = 5, 4, 3
+    U = np.arange(5 * nz * ny * nx, dtype=float).reshape(5, nz, ny, nx) + 1.0
+    G = oracle.fill_ghosts(U, bc)
+    P = G[:, 2:nz + 2, 2:ny + 2, 2:nx + 2]
+    assert np.array_equal(P, U)
+    if bc == oracle.OUTFLOW:
+        lo = lambda n: (0, 0)
+        hi = lambda n: (n - 1, n - 1)
+    else:
+        lo = lambda n: (n - 2, n - 1)
+        hi = lambda n: (0, 1)
+    # x ghosts at proper (y, z)
+    gx = G[:, 2:nz + 2, 2:ny + 2, :]
+    assert np.array_equal(gx[..., 0], U[..., lo(nx)[0]]) and np.array_equal(gx[..., 1], U[..., lo(nx)[1]])
+    assert np.array_equal(gx[..., nx + 2], U[..., hi(nx)[0]]) and np.array_equal(gx[..., nx + 3], U[..., hi(nx)[1]])
+    # y ghosts at proper (x, z)
+    gy = G[:, 2:nz + 2, :, 2:nx + 2]
+    assert np.array_equal(gy[:, :, 0], U[:, :, lo(ny)[0]]) and np.array_equal(gy[:, :, 1], U[:, :, lo(ny)[1]])
+    assert np.array_equal(gy[:, :, ny + 2], U[:, :, hi(ny)[0]]) and np.array_equal(gy[:, :, ny + 3], U[:, :, hi(ny)[1]])
+    # z ghosts at proper (x, y)
+    gz = G[:, :, 2:ny + 2, 2:nx + 2]
+    assert np.array_equal(gz[:, 0], U[:, lo(nz)[0]]) and np.array_equal(gz[:, 1], U[:, lo(nz)[1]])
+    assert np.array_equal(gz[:, nz + 2], U[:, hi(nz)[0]]) and np.array_equal(gz[:, nz + 3], U[:, hi(nz)[1]])
+
+
+def test_periodic_ghosts_of_single_cell_axis():
+    U = np.arange(5 * 2 * 1 * 3, dtype=float).reshape(5, 2, 1, 3) + 1.0
+    G = oracle.fill_ghosts(U, oracle.PERIODIC)
+    for g in (0, 1, 3, 4):   # every y ghost of a 1-cell axis is that cell
+        assert np.array_equal(G[:, 2:4, g, 2:5], U[:, :, 0, :])
+
+
+def test_outflow_wall_flux_is_edge_cell_physical_flux():
+    # Zero-gradient ghosts make both face states at a wall equal to the edge
+    # cell, so the wall flux is that cell's physical flux.  Over one very
+    # short step, the totals of mass and x-momentum then change at the rate
+    # (flux at left wall - flux at right wall) * wall area, to O(dt).
+    n = 16
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    rho = 1.0 + 0.5 * x
+    vx = 0.2 + 0.3 * x
+    p = 1.0 + 0.6 * x
+    U = wl.conserved(rho[None, None, :], vx[None, None, :], 0.0, 0.0, p[None, None, :], (1, 1, n))
+    area, dV = h * h, h ** 3
+    M0 = [math.fsum(U[f].ravel()) * dV for f in range(2)]
+    cfl = 1e-5
+    dts = oracle.run(U, wl.spacing(n, 1, 1), G, cfl, oracle.OUTFLOW, 1)
+    dt = dts[0]
+    rate = [(math.fsum(U[f].ravel()) * dV - M0[f]) / dt for f in range(2)]
+    mass_wall = (rho[0] * vx[0] - rho[-1] * vx[-1]) * area
+    mom_wall = ((rho[0] * vx[0] ** 2 + p[0]) - (rho[-1] * vx[-1] ** 2 + p[-1])) * area
+    assert rate[0] == pytest.approx(mass_wall, rel=1e-3)
+    assert rate[1] == pytest.approx(mom_wall, rel=1e-3)
