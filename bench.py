@@ -1,0 +1,184 @@
+"""Benchmark: FP64 RK2 finite-volume Euler steps per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--size 512]
+                    [--case sine|plane] [--no-cpu-baseline] [--copy-probe MIB]
+
+A step is one RK2 step of the whole hot path on the periodic cube: the two
+fused substep kernels, with the CFL max-reduction fused into the second one
+(the time step stays on the device; one extra reduction pass starts the timed
+sequence).  Inputs are synthetic and already resident in HBM when timing
+starts: the smooth case rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (1,1,1), p = 1
+(exact cell averages), or the seeded random-plane Riemann case (seed 0).
+
+Prints one JSON line with the cell-update rate, the roofline of the dominant
+kernel (per-launch algorithmic HBM bytes over its average event-timed
+duration, against the 8 TB/s HBM3E peak) and the CPU oracle timed on a
+bounded sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_CELL = {0: 80.0,     # substep 1: read U(n), write U(1)
+                  1: 120.0,    # substep 2: read U(1) and U(n), write U(n+1)
+                  2: 40.0}     # dt reduction: read U
+KERNEL_NAMES = {0: "stage_kernel<1> (substep 1)", 1: "stage_kernel<2> (substep 2 + dt max)",
+                2: "rate reduction"}
+METRIC = "cell-updates/s per RK2 step & HBM GB/s; plain FP64 vs chosen forms @ L1 err"
+KERNEL_SOURCES = ["paper_1812_07977_amd/csrc/gs_fluid.hip", "paper_1812_07977_amd/csrc/euler_math.hpp"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, size, case):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_stage_kernels_{size}cubed_{case}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^source_sha256_16:\s*(\w+)", text, re.M)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(rf"^bytes_per_launch_kernel{kernel}:\s*([0-9.eE+]+)", text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def make_input(size, case):
+    import workloads as wl
+    if case == "sine":
+        return wl.sine_wave(size, size, size)
+    return wl.random_plane(size, size, size, seed=0)
+
+
+def cpu_baseline(case, size=256, steps=1):
+    """The oracle as it stands, on a bounded sample: the same case on a
+    size^3 mesh for `steps` RK2 steps, using every host core OpenMP gives it."""
+    import oracle
+    U = make_input(size, case)
+    h = 1.0 / size
+    oracle.lib()
+    t0 = time.perf_counter()
+    taken = len(oracle.run(U, (h, h, h), 1.4, 0.5, oracle.PERIODIC, steps))
+    el = time.perf_counter() - t0
+    return {"value": size ** 3 * taken / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{case} case on a {size}^3 periodic mesh, {taken} RK2 step(s) incl. dt, "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--case", choices=["sine", "plane"], default="sine")
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--chunk-z", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1812_07977_amd import Fluid
+
+    n = args.size
+    print(f"bench: {args.case} {n}^3 periodic, FP64, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    U0 = make_input(n, args.case)
+    U = torch.from_numpy(U0).to("cuda")
+    del U0
+    F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic")
+    F.set_launch(args.tile_y, args.chunk_z)
+
+    if args.copy_probe:
+        nb = args.copy_probe * 1024 * 1024 // 8
+        a = torch.ones(nb, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if args.warmup:
+        F.advance(U, args.warmup)
+    F.sync()
+    F.profile(True)
+    for k in range(3):
+        F.kernel_ms(k)          # discard warm-up events
+
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    F.advance(U, args.steps)
+    t1.record(stream)
+    F.sync()
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    per_kernel = {k: F.kernel_ms(k) for k in range(3)}
+    t_sim = F.time
+    F.close()
+
+    cells = n ** 3
+    ms_per_step = total_ms / args.steps
+    rate = cells * args.steps / (total_ms / 1e3)
+    alg_bytes_step = 200.0 * cells + 40.0 * cells / args.steps
+
+    # dominant kernel: the one with the largest total time
+    dom = max((0, 1), key=lambda k: per_kernel[k][0])
+    ms_sum, launches = per_kernel[dom]
+    avg_s = ms_sum / launches / 1e3
+    achieved = BYTES_PER_CELL[dom] * cells / avg_s / 1e9
+    traffic = measured_traffic(dom, n, args.case)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": KERNEL_NAMES[dom],
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "bytes_per_launch": BYTES_PER_CELL[dom] * cells}
+
+    line = {
+        "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.case} {n}^3 periodic cube, FP64, minmod PLM + HLL + RK2, "
+                               f"CFL 0.5, device dt", "grid": [n, n, n], "case": args.case,
+                   "gamma": 1.4, "cfl": 0.5, "bc": "periodic"},
+        "hbm_gbs_algorithmic": round(alg_bytes_step / (ms_per_step / 1e3) / 1e9, 1),
+        "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
+                              for k, v in per_kernel.items()},
+        "sim_time": t_sim,
+        "roofline": roofline,
+        "context": "paper: ~12X wall-time speedup of one V100 over 7 Power9 cores "
+                   "(Summit, 256^3 per rank, incl. host transfers)",
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/*
+ * gs_fluid.h -- C ABI of libgs_fluid.so: one explicit RK2 finite-volume step
+ * of the 3D ideal-gas Euler equations on a Cartesian mesh, as hand-written
+ * HIP kernels for AMD gfx950 (MI355X), FP64.
+ *
+ * The step is the paper's "Fluid Evolution" loop body (Section 3, Algorithms
+ * 1 and 2): ComputeTimeStep, then two substeps of ComputeDifferences,
+ * ComputeReconstruction, ComputeFluxes and ComputeUpdate combined as
+ *     U(1)   = U(n) + dU(U(n))
+ *     U(n+1) = 0.5 * (U(n) + U(1) + dU(U(1))),
+ * with GhostExchange supplying two ghost layers per side before each
+ * substep.  The paper names these kernels without formulas; this library
+ * computes, in FP64:
+ *   - primitive recovery v = m/rho, p = (gamma-1)(E - m.v/2);
+ *   - differences of primitives (index ranges of the paper's listing in
+ *     Section 3) limited by minmod into slopes sigma; face states
+ *     W_L = W_i + sigma_i/2 and W_R = W_{i+1} - sigma_{i+1}/2;
+ *   - HLL fluxes with Davis signal-speed estimates from the face states;
+ *   - dU = -dt * sum over axes x, y, z of (F(i+1/2) - F(i-1/2)) / h;
+ *   - TimeStep = CFL / max over cells of sum_d (|v_d| + c) / h_d, a
+ *     max-reduction;
+ *   - ghost layers: outflow repeats the edge cell, periodic wraps.  The
+ *     ghosts are virtual (index arithmetic); arrays hold proper cells only.
+ *
+ * Data layout.  A state U is one contiguous device array of doubles
+ * [5][nz][ny][nx], x fastest, fields (rho, m_x, m_y, m_z, E) -- the paper's
+ * StorageForm Value(cell, field) with cells contiguous per field (Section
+ * 2.1).  Pointers must be device pointers (hipMalloc or a PyTorch tensor's
+ * data_ptr()) aligned to 8 bytes (256 recommended), valid on the device that
+ * was current at gs_fluid_create.  The caller owns U and keeps it alive until
+ * the work queued on the handle's stream has finished.
+ *
+ * Streams and synchronisation.  Every call queues work on the handle's
+ * stream (hipStream_t, NULL = the legacy default stream) and returns without
+ * waiting, except gs_fluid_dt, gs_fluid_sync, gs_fluid_get_time and
+ * gs_fluid_kernel_ms, which wait for the stream.  A handle is not
+ * thread-safe: use one handle per stream.
+ *
+ * Errors.  Every int-returning call returns GS_OK or a negative status;
+ * arguments are validated before any HIP call, so bad arguments return
+ * GS_ERR_ARG even on a machine without a GPU.  gs_fluid_last_error gives a
+ * message.  Kernels never fault on bad data: a non-positive or non-finite
+ * density or pressure met in any state the kernels read sets a device flag,
+ * which the next waiting call reports as GS_ERR_NONPHYSICAL (once; the flag
+ * is then cleared).  The affected state holds unspecified finite or NaN
+ * values.
+ */
+#ifndef GS_FLUID_H
+#define GS_FLUID_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_fluid gs_fluid;
+
+/* Boundary kinds (GhostExchange on the physical boundary). */
+enum { GS_BC_OUTFLOW = 0, GS_BC_PERIODIC = 1 };
+
+/* Arithmetic types of the state.  Only FP64 is built. */
+enum { GS_F64 = 0 };
+
+/* Status codes. */
+enum {
+    GS_OK = 0,
+    GS_ERR_ARG = -1,          /* invalid argument; nothing was queued     */
+    GS_ERR_HIP = -2,          /* HIP runtime error or no gfx950 device   */
+    GS_ERR_NONPHYSICAL = -3,  /* rho or p <= 0 or not finite was met     */
+    GS_ERR_STATE = -4         /* call not valid in the handle's state    */
+};
+
+/*
+ * Create a solver for an nx*ny*nz mesh of proper cells with widths dx, dy,
+ * dz, ratio of specific heats gamma (> 1), Courant number cfl (0 < cfl <= 1)
+ * and boundary kind bc, on the current HIP device.  stream is a hipStream_t
+ * or NULL.  Allocates the handle's workspace: one state array (the first
+ * substep's result U(1)) plus a few kilobytes; the handle owns it until
+ * gs_fluid_destroy.  On success *out is the handle; on failure *out is NULL
+ * and gs_fluid_last_error(NULL) gives the reason.  Paper: persistent
+ * device allocation at initialisation (Section 2.1, AllocateDevice), one
+ * device per process (Section 2.2).
+ */
+int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz,
+                    double gamma, double cfl, int bc, int dtype, void* stream,
+                    gs_fluid** out);
+
+/*
+ * ComputeTimeStep (Algorithm 1): *dt_out = cfl / max over proper cells of
+ * sum_d (|v_d| + c)/h_d for state U (device, [5][nz][ny][nx]).  One
+ * reduction pass over U on the stream, then waits for the stream.  Returns
+ * GS_ERR_NONPHYSICAL if U, or any state read since the last waiting call,
+ * held a non-physical cell.
+ */
+int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out);
+
+/*
+ * One RK2 step (Algorithm 1, both substeps) of size dt (finite, > 0): U is
+ * read as U(n) and overwritten in place with U(n+1).  Two kernel launches on
+ * the stream; no host synchronisation.  The handle's device time advances by
+ * dt.
+ */
+int gs_fluid_step(gs_fluid* h, void* U, double dt);
+
+/*
+ * nsteps RK2 steps with the time step computed on the device: before the
+ * first step a reduction pass over U; after that every step's dt comes from
+ * the max-reduction fused into the previous step's second substep.  With
+ * t_end > 0 each dt is clipped to t_end - t (t = the handle's device time)
+ * and steps at or after t_end leave U unchanged.  dt_log, if not NULL, is a
+ * device array of nsteps doubles receiving each step's dt.  No host
+ * synchronisation: the paper's host round trip per step (Algorithm 2) is
+ * replaced by a device-resident dt.
+ */
+int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end,
+                     double* dt_log);
+
+/* Wait for the stream; report a pending non-physical flag. */
+int gs_fluid_sync(gs_fluid* h);
+
+/* Device time: read (waits for the stream) or set (queued on the stream). */
+int gs_fluid_get_time(gs_fluid* h, double* t_out);
+int gs_fluid_set_time(gs_fluid* h, double t);
+
+/* Change the stream used by later calls. */
+int gs_fluid_set_stream(gs_fluid* h, void* stream);
+
+/*
+ * Launch shape of the stage kernels: workgroups of 256 threads own a
+ * (256/tile_y) x tile_y column tile (tile_y 8 or 16; 0 = default 16) and
+ * march chunk_z planes (>= 1; 0 = chosen from the mesh).  Results do not
+ * depend on the shape.
+ */
+int gs_fluid_set_launch(gs_fluid* h, int tile_y, int chunk_z);
+
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around
+ * every stage-kernel launch.  kernel: 0 = first substep, 1 = second substep,
+ * 2 = dt reduction.  gs_fluid_kernel_ms waits for the stream, returns the
+ * summed milliseconds and the number of launches since the last call (or
+ * since enabling), and resets them.
+ */
+int gs_fluid_profile(gs_fluid* h, int enable);
+int gs_fluid_kernel_ms(gs_fluid* h, int kernel, double* total_ms, int* launches);
+
+/* Bytes of device memory the handle allocates for a mesh (workspace). */
+long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype);
+
+/* Release the handle and its workspace (does not wait for the stream; the
+ * caller must not destroy a handle with work in flight).  NULL: no-op. */
+void gs_fluid_destroy(gs_fluid* h);
+
+/* Last error message of the handle, or of the last failed create if h is
+ * NULL.  Never NULL; "" if none. */
+const char* gs_fluid_last_error(const gs_fluid* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_FLUID_H */

@@ -1,0 +1,187 @@
+"""MI355X-native explicit RK2 finite-volume step of the 3D ideal-gas Euler
+equations (FP64), the data-parallel hot path of the Riemann-problem example
+in Budiardja & Cardall, "Targeting GPUs with OpenMP Directives on Summit"
+(arXiv:1812.07977, Section 3, Algorithm 1).
+
+Python view of libgs_fluid.so: `Fluid` marshals torch tensors (device memory)
+and the current stream into the C ABI; all arithmetic runs in the library's
+HIP kernels.  A state is a float64 CUDA/ROCm tensor of shape (5, nz, ny, nx),
+fields (rho, m_x, m_y, m_z, E), x fastest.
+"""
+import ctypes
+
+from . import _lib
+
+__all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC"]
+
+OUTFLOW = _lib.GS_BC_OUTFLOW
+PERIODIC = _lib.GS_BC_PERIODIC
+
+_BC_NAMES = {"outflow": OUTFLOW, "periodic": PERIODIC, OUTFLOW: OUTFLOW, PERIODIC: PERIODIC}
+
+
+class GSError(RuntimeError):
+    """A non-OK status from the library."""
+
+    def __init__(self, status, message):
+        super().__init__(f"gs_fluid status {status}: {message}")
+        self.status = status
+
+
+class NonPhysicalError(GSError):
+    """A state with non-positive or non-finite density or pressure was read."""
+
+
+def _check(status, handle=None):
+    if status == _lib.GS_OK:
+        return
+    msg = _lib.lib().gs_fluid_last_error(handle).decode(errors="replace")
+    if status == _lib.GS_ERR_NONPHYSICAL:
+        raise NonPhysicalError(status, msg)
+    raise GSError(status, msg)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Fluid:
+    """Solver for one mesh of nx*ny*nz proper cells.
+
+    shape   (nx, ny, nz)
+    spacing (dx, dy, dz); default 1/max(shape) in every direction
+    gamma   ratio of specific heats (> 1)
+    cfl     Courant number in (0, 1]
+    bc      "outflow" or "periodic"
+    stream  torch stream for all work (default: the current stream)
+    """
+
+    def __init__(self, shape, spacing=None, gamma=1.4, cfl=0.5, bc="outflow", stream=None):
+        nx, ny, nz = (int(n) for n in shape)
+        if spacing is None:
+            h = 1.0 / max(nx, ny, nz)
+            spacing = (h, h, h)
+        if bc not in _BC_NAMES:
+            raise ValueError(f"unknown boundary kind {bc!r}")
+        self.shape = (nx, ny, nz)
+        self.spacing = tuple(float(s) for s in spacing)
+        self.gamma = float(gamma)
+        self.cfl = float(cfl)
+        self.bc = _BC_NAMES[bc]
+        L = _lib.lib()
+        handle = ctypes.c_void_p()
+        st = _stream_ptr(stream)
+        _check(L.gs_fluid_create(nx, ny, nz, *self.spacing, self.gamma, self.cfl, self.bc,
+                                 _lib.GS_F64, st, ctypes.byref(handle)))
+        self._h = handle
+        self._stream = st
+
+    # -- marshalling ------------------------------------------------------------
+    def _state_ptr(self, U):
+        import torch
+        nx, ny, nz = self.shape
+        if not isinstance(U, torch.Tensor):
+            raise TypeError("U must be a torch tensor")
+        if U.dtype != torch.float64 or not U.is_cuda:
+            raise TypeError("U must be a float64 tensor on the GPU")
+        if tuple(U.shape) != (5, nz, ny, nx) or not U.is_contiguous():
+            raise ValueError(f"U must be contiguous with shape (5, {nz}, {ny}, {nx})")
+        return ctypes.c_void_p(U.data_ptr())
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("Fluid is closed")
+        return self._h
+
+    # -- the C ABI ----------------------------------------------------------------
+    def dt(self, U):
+        """CFL time step of state U (waits for the stream)."""
+        out = ctypes.c_double()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_dt(h, self._state_ptr(U), ctypes.byref(out)), h)
+        return out.value
+
+    def step(self, U, dt):
+        """One RK2 step of size dt, in place (asynchronous)."""
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_step(h, self._state_ptr(U), float(dt)), h)
+
+    def advance(self, U, nsteps, t_end=0.0, dt_log=None):
+        """nsteps RK2 steps with device-computed dt (asynchronous).  dt_log:
+        optional float64 GPU tensor of >= nsteps elements receiving each dt."""
+        import torch
+        h = self._handle()
+        ptr = None
+        if dt_log is not None:
+            if (dt_log.dtype != torch.float64 or not dt_log.is_cuda or not dt_log.is_contiguous()
+                    or dt_log.numel() < nsteps):
+                raise ValueError("dt_log must be a contiguous float64 GPU tensor of >= nsteps")
+            ptr = ctypes.c_void_p(dt_log.data_ptr())
+        _check(_lib.lib().gs_fluid_advance(h, self._state_ptr(U), int(nsteps), float(t_end), ptr), h)
+
+    def sync(self):
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_sync(h), h)
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_get_time(h, ctypes.byref(t)), h)
+        return t.value
+
+    @time.setter
+    def time(self, t):
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_set_time(h, float(t)), h)
+
+    def set_stream(self, stream):
+        h = self._handle()
+        st = _stream_ptr(stream)
+        _check(_lib.lib().gs_fluid_set_stream(h, st), h)
+        self._stream = st
+
+    def set_launch(self, tile_y=0, chunk_z=0):
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_set_launch(h, int(tile_y), int(chunk_z)), h)
+
+    def profile(self, enable=True):
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_profile(h, 1 if enable else 0), h)
+
+    def kernel_ms(self, kernel):
+        """(total ms, launches) of kernel 0 (substep 1), 1 (substep 2) or 2
+        (dt reduction) since the last call; waits for the stream."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_kernel_ms(h, int(kernel), ctypes.byref(ms), ctypes.byref(n)), h)
+        return ms.value, n.value
+
+    @staticmethod
+    def workspace_bytes(shape):
+        nx, ny, nz = shape
+        return _lib.lib().gs_fluid_workspace_bytes(nx, ny, nz, _lib.GS_F64)
+
+    def close(self):
+        """Wait for queued work, then release the handle."""
+        if getattr(self, "_h", None) is not None:
+            L = _lib.lib()
+            L.gs_fluid_sync(self._h)
+            L.gs_fluid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

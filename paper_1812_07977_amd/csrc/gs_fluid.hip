@@ -1,0 +1,854 @@
+// gs_fluid.hip -- gfx950 kernels and C ABI of libgs_fluid.so.
+//
+// One RK2 step is two launches of one fused stage kernel (the paper's
+// Differences -> Reconstruction -> Fluxes -> Update plus the RK combine of
+// Algorithm 1, each substep a single pass), plus a max-reduction for the
+// time step, which the device-dt path fuses into the second substep.
+//
+// Stage kernel design (2.5D march):
+//   * A workgroup of TX*TY threads owns a TX x TY column tile of the mesh and
+//     marches through KZ consecutive z-planes.  Thread (tx, ty) owns cell
+//     column (x0+tx, y0+ty).
+//   * Along z every thread keeps its own column's stencil in registers: the
+//     raw conserved states of planes k, k+1, k+2 (the last one prefetched one
+//     iteration ahead), the left face state of face k+1/2 and the z-flux of
+//     face k-1/2.  Every z-face flux is computed once.
+//   * In the plane, primitives of the tile plus a two-cell halo (a cross: the
+//     stencil never reads corners) are staged in LDS.  Thread (tx, ty)
+//     computes the x-face to its left and the y-face below it; one wave
+//     computes the TX + TY faces on the far edges, so every in-plane face is
+//     also computed once.  Face fluxes go to LDS, and the divergence reads the
+//     two faces of each cell back.
+//   * Ghost cells are virtual: every index outside the mesh is mapped to the
+//     proper cell it copies (outflow) or wraps to (periodic) before loading,
+//     so arrays hold proper cells only and GhostExchange costs no pass.
+//   * HBM traffic per stage is one read of the stage input, one write of the
+//     output and, in the second stage, one read of U(n); halo re-reads are
+//     served by L2 when neighbouring tiles run on the same XCD, for which the
+//     workgroup -> tile map gives each XCD a contiguous band of tile rows and
+//     walks all XCDs through the same z-chunk at the same time.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "euler_math.hpp"
+#include "gs_fluid.h"
+
+namespace gs {
+
+// Mesh geometry and tiling, passed by value.
+struct Geom {
+    int nx, ny, nz;
+    int periodic;
+    int plane;          // nx * ny
+    long long field;    // nx * ny * nz: distance between fields
+    int ntx, nty;       // tiles along x, y
+    int kz, nchunk;     // planes per chunk, chunks along z
+    int band;           // tiles per XCD band (0: plain block order)
+};
+
+// Device-resident words of a handle.  rate[] and t[] are ping-pong pairs
+// indexed by the step parity: step s reads slot s&1 and prepares slot
+// (s+1)&1, so no kernel ever reads a word another kernel of the same step
+// writes.  rate holds the IEEE bits of a non-negative double, so an unsigned
+// max is a floating-point max.
+struct DevState {
+    unsigned long long rate[2];
+    double t[2];
+    unsigned long long rate_dt;  // result slot of the dt reduction
+    unsigned int flags;          // bit 0: a non-physical cell was read
+    unsigned int pad;
+};
+
+__device__ __forceinline__ int map_index(int i, int n, int periodic)
+{
+    if (periodic) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Workgroup -> (tile x, tile y, chunk).  Workgroups are dispatched to the 8
+// XCDs round-robin; with band > 0 the n-th workgroup an XCD receives works on
+// chunk n / band of that XCD's band of tiles, so at any moment the XCDs hold
+// adjacent bands of the same z-chunk.
+__device__ __forceinline__ void block_tile(const Geom& g, int& tx0, int& ty0, int& kc)
+{
+    int b = blockIdx.x;
+    int tile, chunk;
+    if (g.band > 0) {
+        int xcd = b & 7, n = b >> 3;
+        chunk = n / g.band;
+        tile = xcd * g.band + (n - chunk * g.band);
+    } else {
+        int ntile = g.ntx * g.nty;
+        chunk = b / ntile;
+        tile = b - chunk * ntile;
+    }
+    int ty = tile / g.ntx;
+    tx0 = tile - ty * g.ntx;
+    ty0 = ty;
+    kc = chunk;
+}
+
+__device__ __forceinline__ void load5(const double* __restrict__ base, long long field, int off,
+                                      double u[NV])
+{
+#pragma unroll
+    for (int f = 0; f < NV; ++f) u[f] = base[f * field + off];
+}
+
+// Fused RK2 substep.  STAGE 1: Uout = Uin + dU(Uin).  STAGE 2: Uout =
+// 0.5 ((Un + Uin) + dU(Uin)), where Uout may alias Un (each cell's Un is read
+// only by the thread that writes it).  DEVDT: dt = cfl / max rate (slot
+// parity), clipped to t_end; else dt = dt_host.  RATE: accumulate the max
+// signal rate of Uout into rate[parity ^ 1].
+#ifndef GS_STAGE_WAVES_PER_EU
+#define GS_STAGE_WAVES_PER_EU 2
+#endif
+
+template <int TX, int TY, int STAGE, bool DEVDT, bool RATE>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(GS_STAGE_WAVES_PER_EU)))
+stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geom g, Phys k,
+             DevState* __restrict__ st, int parity, double dt_host, double t_end,
+             double* __restrict__ dt_log, int step)
+{
+    constexpr int NT = TX * TY;
+    constexpr int WX = TX + 4, WY = TY + 4;
+    static_assert(4 * (TX + TY) <= NT, "one halo cell per thread at most");
+    static_assert(TX + TY <= NT, "one edge face per thread at most");
+    __shared__ double Ws[NV][WY][WX];     // primitives of the plane, +2 halo
+    __shared__ double Fx[NV][TY][TX + 1]; // x-face fluxes, face i-1/2 at [i]
+    __shared__ double Fy[NV][TY + 1][TX]; // y-face fluxes, face j-1/2 at [j]
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+
+    int tix, tiy, kc;
+    block_tile(g, tix, tiy, kc);
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int z0 = kc * g.kz;
+    const int z1 = min(z0 + g.kz, g.nz);
+
+    // own column (ghost columns of ragged tiles map to valid cells)
+    const int i = x0 + tx, j = y0 + ty;
+    const bool active = (i < g.nx) & (j < g.ny);
+    const int own = map_index(j, g.ny, g.periodic) * g.nx + map_index(i, g.nx, g.periodic);
+
+    // halo role: 4 cells per tile row (x) and per tile column (y)
+    int hxl = 0, hyl = 0, hoff = 0;
+    bool halo = false;
+    if (tid < 4 * TY) {
+        int q = tid & 3;
+        hyl = tid >> 2;
+        hxl = q < 2 ? q - 2 : TX + q - 2;
+        halo = true;
+    } else if (tid < 4 * TY + 4 * TX) {
+        int h = tid - 4 * TY;
+        int q = h / TX;
+        hxl = h - q * TX;
+        hyl = q < 2 ? q - 2 : TY + q - 2;
+        halo = true;
+    }
+    if (halo)
+        hoff = map_index(y0 + hyl, g.ny, g.periodic) * g.nx + map_index(x0 + hxl, g.nx, g.periodic);
+
+    // edge-face role: the last TX + TY threads
+    const int e = tid - (NT - (TX + TY));
+
+    // time step
+    double dt = dt_host;
+    const double t_now = st->t[parity];
+    if (DEVDT) {
+        double rate = __longlong_as_double((long long)st->rate[parity]);
+        dt = k.cfl / rate;
+        if (t_end > 0.0) {
+            if (!(t_now < t_end)) dt = 0.0;
+            else if (t_now + dt > t_end) dt = t_end - t_now;
+        }
+    }
+    if (STAGE == 1 && blockIdx.x == 0 && tid == 0) {
+        st->t[parity ^ 1] = t_now + dt;
+        st->rate[parity ^ 1] = 0ull;
+        if (dt_log) dt_log[step] = dt;
+    }
+
+    const long long F = g.field;
+    auto plane_ptr = [&](const double* base, int z) {
+        return base + (long long)map_index(z, g.nz, g.periodic) * g.plane;
+    };
+
+    bool bad = false;
+    double rmax = 0.0;
+
+    // ---- prologue: planes z0-2 .. z0+2 of the own column, halo of z0 ----
+    double Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
+    double WLz[NV], Fm[NV];
+    {
+        double Um2[NV], Um1[NV];
+        load5(plane_ptr(Uin, z0 - 2), F, own, Um2);
+        load5(plane_ptr(Uin, z0 - 1), F, own, Um1);
+        load5(plane_ptr(Uin, z0), F, own, Uk);
+        load5(plane_ptr(Uin, z0 + 1), F, own, Uk1);
+        load5(plane_ptr(Uin, z0 + 2), F, own, Uk2);
+        if (halo) load5(plane_ptr(Uin, z0), F, hoff, Hk);
+        double Wm2[NV], Wm1[NV], W0[NV], W1[NV];
+        bad |= !cons_to_prim(Um2, Wm2, k);
+        bad |= !cons_to_prim(Um1, Wm1, k);
+        bad |= !cons_to_prim(Uk, W0, k);
+        bad |= !cons_to_prim(Uk1, W1, k);
+        face_flux<2>(Wm2, Wm1, W0, W1, k, Fm);  // face z0 - 1/2
+        double Wp2[NV];
+        bad |= !cons_to_prim(Uk2, Wp2, k);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            WLz[v] = __builtin_fma(0.5, minmod(W0[v] - Wm1[v], W1[v] - W0[v]), W0[v]);
+    }
+
+    for (int z = z0; z < z1; ++z) {
+        // prefetch plane z+3 of the own column and the halo of plane z+1
+        double Uk3[NV], Hk1[NV], Uo[NV];
+        load5(plane_ptr(Uin, z + 3), F, own, Uk3);
+        if (halo) load5(plane_ptr(Uin, z + 1), F, hoff, Hk1);
+        if (STAGE == 2) load5(Un + (long long)z * g.plane, F, own, Uo);
+
+        // stage the plane's primitives in LDS
+        {
+            double w[NV];
+            cons_to_prim(Uk, w, k);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = w[v];
+            if (halo) {
+                cons_to_prim(Hk, w, k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
+            }
+        }
+        __syncthreads();
+
+        // in-plane faces: x-face left of the own cell, y-face below it
+        {
+            double a[NV], b[NV], c[NV], d[NV], f[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a[v] = Ws[v][ty + 2][tx];
+                b[v] = Ws[v][ty + 2][tx + 1];
+                c[v] = Ws[v][ty + 2][tx + 2];
+                d[v] = Ws[v][ty + 2][tx + 3];
+            }
+            face_flux<0>(a, b, c, d, k, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fx[v][ty][tx] = f[v];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a[v] = Ws[v][ty][tx + 2];
+                b[v] = Ws[v][ty + 1][tx + 2];
+                d[v] = Ws[v][ty + 3][tx + 2];
+            }
+            face_flux<1>(a, b, c, d, k, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fy[v][ty][tx] = f[v];
+        }
+        // faces on the far edges of the tile
+        if (e >= 0) {
+            double a[NV], b[NV], c[NV], d[NV], f[NV];
+            if (e < TX) {  // y-face between rows TY-1 and TY, column e
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    a[v] = Ws[v][TY][e + 2];
+                    b[v] = Ws[v][TY + 1][e + 2];
+                    c[v] = Ws[v][TY + 2][e + 2];
+                    d[v] = Ws[v][TY + 3][e + 2];
+                }
+                face_flux<1>(a, b, c, d, k, f);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Fy[v][TY][e] = f[v];
+            } else {       // x-face between columns TX-1 and TX, row e - TX
+                const int r = e - TX;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    a[v] = Ws[v][r + 2][TX];
+                    b[v] = Ws[v][r + 2][TX + 1];
+                    c[v] = Ws[v][r + 2][TX + 2];
+                    d[v] = Ws[v][r + 2][TX + 3];
+                }
+                face_flux<0>(a, b, c, d, k, f);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Fx[v][r][TX] = f[v];
+            }
+        }
+        __syncthreads();
+
+        // z-face above the own cell, from the register queue
+        double Fp[NV], WLn[NV];
+        {
+            double W0[NV], W1[NV], W2[NV], R[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) W0[v] = Ws[v][ty + 2][tx + 2];
+            cons_to_prim(Uk1, W1, k);
+            bad |= !cons_to_prim(Uk2, W2, k);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double d1 = W1[v] - W0[v], d2 = W2[v] - W1[v];
+                double s1 = minmod(d1, d2);
+                R[v] = __builtin_fma(-0.5, s1, W1[v]);
+                WLn[v] = __builtin_fma(0.5, s1, W1[v]);
+            }
+            hll_flux<2>(WLz, R, k, Fp);
+        }
+
+        // divergence, RK combine, store
+        {
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double acc = (Fx[v][ty][tx + 1] - Fx[v][ty][tx]) * k.inv_h[0];
+                acc = acc + (Fy[v][ty + 1][tx] - Fy[v][ty][tx]) * k.inv_h[1];
+                acc = acc + (Fp[v] - Fm[v]) * k.inv_h[2];
+                double du = -dt * acc;
+                if (STAGE == 1)
+                    out[v] = Uk[v] + du;
+                else
+                    out[v] = 0.5 * ((Uo[v] + Uk[v]) + du);
+            }
+            if (active) {
+                double* po = Uout + (long long)z * g.plane + own;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) po[v * F] = out[v];
+            }
+            if (RATE && active) {
+                double w[NV];
+                cons_to_prim(out, w, k);
+                rmax = __builtin_fmax(rmax, signal_rate(w, k));
+            }
+        }
+
+        // rotate the queue
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Uk[v] = Uk1[v];
+            Uk1[v] = Uk2[v];
+            Uk2[v] = Uk3[v];
+            Hk[v] = Hk1[v];
+            WLz[v] = WLn[v];
+            Fm[v] = Fp[v];
+        }
+    }
+
+    // epilogue: flags and the max signal rate, one atomic per wavefront
+    if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
+    if (RATE) {
+        for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
+        if ((tid & 63) == 0)
+            atomicMax(&st->rate[parity ^ 1], (unsigned long long)__double_as_longlong(rmax));
+    }
+}
+
+// Max signal rate over all cells of U (first pass: one partial per block) and
+// the non-physical flag.
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 1024;
+
+__global__ void __launch_bounds__(RED_THREADS)
+rate_partial_kernel(const double* __restrict__ U, long long ncell, Phys k,
+                    double* __restrict__ partial, DevState* __restrict__ st)
+{
+    __shared__ double red[RED_THREADS / 64];
+    double rmax = 0.0;
+    bool bad = false;
+    for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * RED_THREADS) {
+        double u[NV], w[NV];
+#pragma unroll
+        for (int f = 0; f < NV; ++f) u[f] = U[f * ncell + c];
+        bad |= !cons_to_prim(u, w, k);
+        rmax = __builtin_fmax(rmax, signal_rate(w, k));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->flags, 1u);
+    for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < RED_THREADS / 64; ++w) m = __builtin_fmax(m, red[w]);
+        partial[blockIdx.x] = m;
+    }
+}
+
+// Second pass: max of the partials into *dst (as IEEE bits).
+__global__ void __launch_bounds__(RED_THREADS)
+rate_final_kernel(const double* __restrict__ partial, int n, unsigned long long* dst)
+{
+    __shared__ double red[RED_THREADS / 64];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += RED_THREADS) m = __builtin_fmax(m, partial[i]);
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < RED_THREADS / 64; ++w) m = __builtin_fmax(m, red[w]);
+        m = __builtin_fmax(red[0], m);
+        *dst = (unsigned long long)__double_as_longlong(m);
+    }
+}
+
+// Small state writes, as kernels so that the host never records a memset.
+__global__ void init_state_kernel(DevState* st)
+{
+    st->rate[0] = st->rate[1] = 0ull;
+    st->t[0] = st->t[1] = 0.0;
+    st->rate_dt = 0ull;
+    st->flags = 0u;
+    st->pad = 0u;
+}
+
+__global__ void set_time_kernel(DevState* st, int parity, double t) { st->t[parity] = t; }
+
+__global__ void clear_flags_kernel(DevState* st) { st->flags = 0u; }
+
+}  // namespace gs
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum { K_STAGE1 = 0, K_STAGE2 = 1, K_RATE = 2, K_COUNT = 3 };
+
+}  // namespace
+
+struct gs_fluid {
+    int nx, ny, nz;
+    double h[3];
+    double gamma, cfl;
+    int bc;
+    int device;
+    hipStream_t stream;
+    double* U1;            // first-substep result (workspace)
+    double* partial;       // dt-reduction partials
+    DevState* st;          // device words
+    DevState* host_st;     // pinned host mirror for waiting calls
+    int parity;
+    int tile_y, chunk_z;   // launch shape (0 = default)
+    std::string err;
+    bool profile;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[K_COUNT];
+};
+
+namespace {
+
+int fail(gs_fluid* h, int code, const std::string& msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_fail(gs_fluid* h, hipError_t e, const char* what)
+{
+    return fail(h, GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+Phys make_phys(const gs_fluid* h)
+{
+    Phys k;
+    k.gamma = h->gamma;
+    k.gm1 = h->gamma - 1.0;
+    k.inv_gm1 = 1.0 / (h->gamma - 1.0);
+    for (int d = 0; d < 3; ++d) k.inv_h[d] = 1.0 / h->h[d];
+    k.cfl = h->cfl;
+    return k;
+}
+
+struct Launch {
+    Geom g;
+    int tx, ty;
+    int blocks;
+};
+
+Launch make_launch(const gs_fluid* h)
+{
+    Launch L;
+    L.ty = (h->tile_y == 0) ? 16 : h->tile_y;
+    L.tx = 256 / L.ty;
+    Geom& g = L.g;
+    g.nx = h->nx;
+    g.ny = h->ny;
+    g.nz = h->nz;
+    g.periodic = (h->bc == GS_BC_PERIODIC);
+    g.plane = h->nx * h->ny;
+    g.field = (long long)h->nx * h->ny * h->nz;
+    g.ntx = (h->nx + L.tx - 1) / L.tx;
+    g.nty = (h->ny + L.ty - 1) / L.ty;
+    const int ntile = g.ntx * g.nty;
+    int kz = h->chunk_z;
+    if (kz <= 0) {
+        // aim for about 2048 workgroups (several per CU slot), chunks of at
+        // least 8 planes
+        long long want_chunks = (2048 + ntile - 1) / ntile;
+        kz = (int)((h->nz + want_chunks - 1) / want_chunks);
+        if (kz < 8) kz = 8;
+    }
+    if (kz > h->nz) kz = h->nz;
+    g.kz = kz;
+    g.nchunk = (h->nz + kz - 1) / kz;
+    g.band = (ntile % 8 == 0) ? ntile / 8 : 0;
+    L.blocks = ntile * g.nchunk;
+    return L;
+}
+
+hipEvent_t take_event(gs_fluid* h)
+{
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a start event if profiling; returns it (or null).
+hipEvent_t prof_begin(gs_fluid* h)
+{
+    if (!h->profile) return nullptr;
+    hipEvent_t e = take_event(h);
+    if (e) (void)hipEventRecord(e, h->stream);
+    return e;
+}
+
+void prof_end(gs_fluid* h, int kernel, hipEvent_t start)
+{
+    if (!h->profile || !start) return;
+    hipEvent_t e = take_event(h);
+    if (!e) return;
+    (void)hipEventRecord(e, h->stream);
+    h->ev_used[kernel].push_back({start, e});
+}
+
+template <int TX, int TY>
+hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, bool rate,
+                          const double* Uin, const double* Un, double* Uout, double dt_host,
+                          double t_end, double* dt_log, int step)
+{
+    const Phys k = make_phys(h);
+    dim3 grid(L.blocks), block(TX * TY);
+#define GS_LAUNCH(S, D, R)                                                                      \
+    hipLaunchKernelGGL((stage_kernel<TX, TY, S, D, R>), grid, block, 0, h->stream, Uin, Un, Uout, \
+                       L.g, k, h->st, h->parity, dt_host, t_end, dt_log, step)
+    if (stage == 1) {
+        if (devdt) GS_LAUNCH(1, true, false);
+        else GS_LAUNCH(1, false, false);
+    } else {
+        if (devdt) {
+            if (rate) GS_LAUNCH(2, true, true);
+            else GS_LAUNCH(2, true, false);
+        } else {
+            if (rate) GS_LAUNCH(2, false, true);
+            else GS_LAUNCH(2, false, false);
+        }
+    }
+#undef GS_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(gs_fluid* h, int stage, bool devdt, bool rate, const double* Uin,
+                        const double* Un, double* Uout, double dt_host, double t_end,
+                        double* dt_log, int step)
+{
+    Launch L = make_launch(h);
+    hipEvent_t ev = prof_begin(h);
+    hipError_t e;
+    if (L.ty == 8)
+        e = launch_stage_t<32, 8>(h, L, stage, devdt, rate, Uin, Un, Uout, dt_host, t_end, dt_log, step);
+    else
+        e = launch_stage_t<16, 16>(h, L, stage, devdt, rate, Uin, Un, Uout, dt_host, t_end, dt_log, step);
+    prof_end(h, stage == 1 ? K_STAGE1 : K_STAGE2, ev);
+    return e;
+}
+
+hipError_t launch_rate(gs_fluid* h, const double* U, unsigned long long* dst)
+{
+    const long long ncell = (long long)h->nx * h->ny * h->nz;
+    long long want = (ncell + RED_THREADS - 1) / RED_THREADS;
+    int blocks = (int)(want < RED_BLOCKS ? want : RED_BLOCKS);
+    hipEvent_t ev = prof_begin(h);
+    hipLaunchKernelGGL(rate_partial_kernel, dim3(blocks), dim3(RED_THREADS), 0, h->stream, U, ncell,
+                       make_phys(h), h->partial, h->st);
+    hipLaunchKernelGGL(rate_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, h->partial,
+                       blocks, dst);
+    prof_end(h, K_RATE, ev);
+    return hipGetLastError();
+}
+
+// Waits for the stream and copies the device words to the pinned mirror;
+// reports (once) a pending non-physical flag.
+int sync_state(gs_fluid* h)
+{
+    hipError_t e = hipMemcpyAsync(h->host_st, h->st, sizeof(DevState), hipMemcpyDeviceToHost,
+                                  h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    if (h->host_st->flags) {
+        hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(1), 0, h->stream, h->st);
+        return fail(h, GS_ERR_NONPHYSICAL,
+                    "non-physical state (rho or p not positive, or not finite) was read");
+    }
+    return GS_OK;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+// Device address of a word of the handle's DevState.
+unsigned long long* rate_slot(gs_fluid* h, int which)
+{
+    char* base = (char*)h->st;
+    if (which < 0) return (unsigned long long*)(base + offsetof(DevState, rate_dt));
+    return (unsigned long long*)(base + offsetof(DevState, rate) + which * sizeof(unsigned long long));
+}
+
+}  // namespace
+
+extern "C" {
+
+long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || dtype != GS_F64) return -1;
+    long long ncell = (long long)nx * ny * nz;
+    return ncell * NV * (long long)sizeof(double) + RED_BLOCKS * (long long)sizeof(double) +
+           (long long)sizeof(DevState);
+}
+
+int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, double gamma,
+                    double cfl, int bc, int dtype, void* stream, gs_fluid** out)
+{
+    g_create_error.clear();
+    if (!out) return fail(nullptr, GS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
+    if ((long long)nx * ny > (1LL << 30) ||
+        (long long)nx * ny * nz * NV > (1LL << 40))
+        return fail(nullptr, GS_ERR_ARG, "mesh too large");
+    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
+        return fail(nullptr, GS_ERR_ARG, "cell widths must be finite and > 0");
+    if (!std::isfinite(gamma) || !(gamma > 1.0))
+        return fail(nullptr, GS_ERR_ARG, "gamma must be finite and > 1");
+    if (!std::isfinite(cfl) || !(cfl > 0.0) || cfl > 1.0)
+        return fail(nullptr, GS_ERR_ARG, "cfl must be in (0, 1]");
+    if (bc != GS_BC_OUTFLOW && bc != GS_BC_PERIODIC)
+        return fail(nullptr, GS_ERR_ARG, "unknown boundary kind");
+    if (dtype != GS_F64) return fail(nullptr, GS_ERR_ARG, "unsupported dtype (only GS_F64)");
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, GS_ERR_HIP,
+                    std::string("built for gfx950, device is ") + prop.gcnArchName);
+
+    gs_fluid* h = new gs_fluid();
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->h[0] = dx;
+    h->h[1] = dy;
+    h->h[2] = dz;
+    h->gamma = gamma;
+    h->cfl = cfl;
+    h->bc = bc;
+    h->device = dev;
+    h->stream = (hipStream_t)stream;
+    h->U1 = nullptr;
+    h->partial = nullptr;
+    h->st = nullptr;
+    h->host_st = nullptr;
+    h->parity = 0;
+    h->tile_y = 0;
+    h->chunk_z = 0;
+    h->profile = false;
+
+    const size_t state_bytes = (size_t)nx * ny * nz * NV * sizeof(double);
+    if ((e = hipMalloc((void**)&h->U1, state_bytes)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->partial, RED_BLOCKS * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&h->st, sizeof(DevState))) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h->host_st, sizeof(DevState), hipHostMallocDefault)) !=
+            hipSuccess) {
+        int r = hip_fail(nullptr, e, "allocation");
+        gs_fluid_destroy(h);
+        return r;
+    }
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st);
+    if ((e = hipGetLastError()) != hipSuccess) {
+        int r = hip_fail(nullptr, e, "init kernel");
+        gs_fluid_destroy(h);
+        return r;
+    }
+    *out = h;
+    return GS_OK;
+}
+
+int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (!dt_out) return fail(h, GS_ERR_ARG, "dt_out is NULL");
+    hipError_t e = launch_rate(h, (const double*)U, rate_slot(h, -1));
+    if (e != hipSuccess) return hip_fail(h, e, "dt reduction launch");
+    int r = sync_state(h);
+    if (r != GS_OK) return r;
+    double rate = __builtin_bit_cast(double, h->host_st->rate_dt);
+    if (!(rate > 0.0) || !std::isfinite(rate))
+        return fail(h, GS_ERR_NONPHYSICAL, "signal rate is not positive and finite");
+    *dt_out = h->cfl / rate;
+    return GS_OK;
+}
+
+int gs_fluid_step(gs_fluid* h, void* U, double dt)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (!finite_pos(dt)) return fail(h, GS_ERR_ARG, "dt must be finite and > 0");
+    double* u = (double*)U;
+    hipError_t e = launch_stage(h, 1, false, false, u, u, h->U1, dt, 0.0, nullptr, 0);
+    if (e == hipSuccess) e = launch_stage(h, 2, false, false, h->U1, u, u, dt, 0.0, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+    h->parity ^= 1;
+    return GS_OK;
+}
+
+int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end, double* dt_log)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (nsteps < 0) return fail(h, GS_ERR_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(t_end) || t_end < 0.0) return fail(h, GS_ERR_ARG, "t_end must be finite and >= 0");
+    if (dt_log && !aligned8(dt_log)) return fail(h, GS_ERR_ARG, "dt_log not 8-byte aligned");
+    if (nsteps == 0) return GS_OK;
+    double* u = (double*)U;
+    hipError_t e = launch_rate(h, u, rate_slot(h, h->parity));
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+        e = launch_stage(h, 1, true, false, u, u, h->U1, 0.0, t_end, dt_log, s);
+        if (e == hipSuccess) e = launch_stage(h, 2, true, true, h->U1, u, u, 0.0, t_end, dt_log, s);
+        h->parity ^= 1;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "advance launch");
+    return GS_OK;
+}
+
+int gs_fluid_sync(gs_fluid* h)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    return sync_state(h);
+}
+
+int gs_fluid_get_time(gs_fluid* h, double* t_out)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!t_out) return fail(h, GS_ERR_ARG, "t_out is NULL");
+    int r = sync_state(h);
+    *t_out = h->host_st->t[h->parity];
+    return r;
+}
+
+int gs_fluid_set_time(gs_fluid* h, double t)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!std::isfinite(t)) return fail(h, GS_ERR_ARG, "t must be finite");
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(1), 0, h->stream, h->st, h->parity, t);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GS_OK : hip_fail(h, e, "set_time");
+}
+
+int gs_fluid_set_stream(gs_fluid* h, void* stream)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    h->stream = (hipStream_t)stream;
+    return GS_OK;
+}
+
+int gs_fluid_set_launch(gs_fluid* h, int tile_y, int chunk_z)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (tile_y != 0 && tile_y != 8 && tile_y != 16)
+        return fail(h, GS_ERR_ARG, "tile_y must be 0, 8 or 16");
+    if (chunk_z < 0) return fail(h, GS_ERR_ARG, "chunk_z must be >= 0");
+    h->tile_y = tile_y;
+    h->chunk_z = chunk_z;
+    return GS_OK;
+}
+
+int gs_fluid_profile(gs_fluid* h, int enable)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    h->profile = enable != 0;
+    return GS_OK;
+}
+
+int gs_fluid_kernel_ms(gs_fluid* h, int kernel, double* total_ms, int* launches)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (kernel < 0 || kernel >= K_COUNT) return fail(h, GS_ERR_ARG, "kernel must be 0, 1 or 2");
+    if (!total_ms || !launches) return fail(h, GS_ERR_ARG, "output pointer is NULL");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    double sum = 0.0;
+    int n = 0;
+    for (auto& pr : h->ev_used[kernel]) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+            sum += ms;
+            ++n;
+        }
+        h->ev_pool.push_back(pr.first);
+        h->ev_pool.push_back(pr.second);
+    }
+    h->ev_used[kernel].clear();
+    *total_ms = sum;
+    *launches = n;
+    return GS_OK;
+}
+
+void gs_fluid_destroy(gs_fluid* h)
+{
+    if (!h) return;
+    for (auto& v : h->ev_used)
+        for (auto& pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->U1) (void)hipFree(h->U1);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->st) (void)hipFree(h->st);
+    if (h->host_st) (void)hipHostFree(h->host_st);
+    delete h;
+}
+
+const char* gs_fluid_last_error(const gs_fluid* h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

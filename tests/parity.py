@@ -1,0 +1,80 @@
+"""Helpers shared by the GPU parity tests: running the same seeded input
+through the oracle (CPU) and the HIP library (GPU) and comparing them."""
+import numpy as np
+
+import oracle
+
+GAMMA = 1.4
+CFL = 0.5
+BC = {"outflow": oracle.OUTFLOW, "periodic": oracle.PERIODIC}
+
+
+def rel_linf(gpu, ref):
+    """Per-field max |gpu - ref| / max |ref|; a field whose reference is
+    identically zero is scaled by the largest field maximum instead."""
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    scale_all = np.max(np.abs(ref))
+    out = []
+    for f in range(ref.shape[0]):
+        s = np.max(np.abs(ref[f]))
+        if s == 0.0:
+            s = scale_all
+        out.append(float(np.max(np.abs(gpu[f] - ref[f])) / s))
+    return out
+
+
+def to_gpu(U):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+
+
+def to_cpu(T):
+    import torch
+    torch.cuda.synchronize()
+    return T.cpu().numpy()
+
+
+def oracle_run(U0, bc, nsteps, t_end=0.0, spacing=None):
+    U = U0.copy()
+    nz, ny, nx = U.shape[1:]
+    if spacing is None:
+        h = 1.0 / max(nx, ny, nz)
+        spacing = (h, h, h)
+    dts = oracle.run(U, spacing, GAMMA, CFL, BC[bc], nsteps, t_end)
+    return U, dts
+
+
+def gpu_run_host_dt(U0, bc, nsteps, launch=None):
+    """dt from gs_fluid_dt, then gs_fluid_step, nsteps times."""
+    from paper_1812_07977_amd import Fluid
+    nz, ny, nx = U0.shape[1:]
+    U = to_gpu(U0)
+    dts = []
+    with Fluid((nx, ny, nz), gamma=GAMMA, cfl=CFL, bc=bc) as F:
+        if launch:
+            F.set_launch(*launch)
+        for _ in range(nsteps):
+            dt = F.dt(U)
+            dts.append(dt)
+            F.step(U, dt)
+        F.sync()
+        out = to_cpu(U)
+    return out, np.array(dts)
+
+
+def gpu_run_device_dt(U0, bc, nsteps, t_end=0.0, launch=None):
+    """gs_fluid_advance: dt on the device; returns (U, dts, final time)."""
+    import torch
+    from paper_1812_07977_amd import Fluid
+    nz, ny, nx = U0.shape[1:]
+    U = to_gpu(U0)
+    log = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+    with Fluid((nx, ny, nz), gamma=GAMMA, cfl=CFL, bc=bc) as F:
+        if launch:
+            F.set_launch(*launch)
+        F.advance(U, nsteps, t_end, log)
+        t = F.time
+        out = to_cpu(U)
+        dts = log.cpu().numpy()[:nsteps]
+    return out, dts, t

@@ -1,0 +1,121 @@
+"""The C ABI on the CPU: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching HIP (so these run
+without a GPU).  Also checks that the product never reaches the oracle."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs_fluid.h")
+
+lib_mod = pytest.importorskip("paper_1812_07977_amd._lib")
+
+
+def _lib():
+    try:
+        return lib_mod.lib()
+    except lib_mod.LibraryMissing as e:
+        pytest.fail(str(e))
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_fluid_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_signatures():
+    names = [n for n, _, _ in lib_mod.SIGNATURES]
+    assert sorted(names) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+G_OK = dict(nx=8, ny=8, nz=8, dx=0.125, dy=0.125, dz=0.125, gamma=1.4, cfl=0.5, bc=0, dtype=0)
+
+
+def _create(**over):
+    a = dict(G_OK)
+    a.update(over)
+    h = ctypes.c_void_p()
+    st = _lib().gs_fluid_create(a["nx"], a["ny"], a["nz"], a["dx"], a["dy"], a["dz"], a["gamma"],
+                                a["cfl"], a["bc"], a["dtype"], None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("over", [
+    dict(nx=0), dict(ny=-1), dict(nz=0),
+    dict(dx=0.0), dict(dy=-0.1), dict(dz=math.inf), dict(dx=math.nan),
+    dict(gamma=1.0), dict(gamma=0.5), dict(gamma=math.nan),
+    dict(cfl=0.0), dict(cfl=1.5), dict(cfl=math.nan),
+    dict(bc=2), dict(bc=-1), dict(dtype=1),
+    dict(nx=1 << 16, ny=1 << 16, nz=2),
+])
+def test_create_rejects_bad_arguments(over):
+    st, h = _create(**over)
+    assert st == lib_mod.GS_ERR_ARG
+    assert not h.value
+    assert _lib().gs_fluid_last_error(None).decode()
+
+
+def test_create_rejects_null_out():
+    L = _lib()
+    st = L.gs_fluid_create(8, 8, 8, 0.1, 0.1, 0.1, 1.4, 0.5, 0, 0, None, None)
+    assert st == lib_mod.GS_ERR_ARG
+
+
+def test_null_handle_calls_are_argument_errors():
+    L = _lib()
+    d = ctypes.c_double()
+    n = ctypes.c_int()
+    assert L.gs_fluid_dt(None, None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_step(None, None, 0.1) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_advance(None, None, 1, 0.0, None) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_sync(None) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_get_time(None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_set_time(None, 0.0) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_set_stream(None, None) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_set_launch(None, 0, 0) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_profile(None, 1) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_kernel_ms(None, 0, ctypes.byref(d), ctypes.byref(n)) == lib_mod.GS_ERR_ARG
+    L.gs_fluid_destroy(None)
+    assert L.gs_fluid_last_error(None) is not None
+
+
+def test_workspace_bytes():
+    L = _lib()
+    n = 10 * 20 * 30
+    ws = L.gs_fluid_workspace_bytes(10, 20, 30, 0)
+    assert ws >= n * 5 * 8            # one state array
+    assert ws - n * 5 * 8 < 64 * 1024  # plus a few kilobytes
+    assert L.gs_fluid_workspace_bytes(0, 1, 1, 0) == -1
+    assert L.gs_fluid_workspace_bytes(1, 1, 1, 7) == -1
+
+
+def test_valid_create_without_gpu_is_a_hip_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _create()
+    assert st == lib_mod.GS_ERR_HIP
+    assert not h.value
+
+
+def test_product_code_never_reaches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1812_07977_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b|gs_oracle|ora_", text), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c")):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1812_07977_amd" not in text and "gs_fluid" not in text, f

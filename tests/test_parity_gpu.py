@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+inputs, through the C ABI.
+
+Bar: every conserved field within 1e-12 relative L-infinity of the oracle
+(max |gpu - oracle| / max |oracle| per field, a zero field scaled by the
+largest field), and every step's dt within 1e-14 relative.  The GPU divides
+with a refined hardware reciprocal and takes square roots through a refined
+reciprocal square root; both are accurate to a few ulp, and every operation
+of the scheme is Lipschitz (minmod, min/max speeds, the clamped HLL
+average), so differences stay at the rounding level.  Where a result must be
+bit-identical (uniform states, tile shapes, repeated runs, the two dt paths)
+the test says so.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests.parity import (CFL, GAMMA, gpu_run_device_dt, gpu_run_host_dt, oracle_run, rel_linf,
+                          to_cpu, to_gpu)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+DT_TOL = 1e-14
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _assert_parity(gpu, ref, tol=TOL, what=""):
+    errs = rel_linf(gpu, ref)
+    assert max(errs) <= tol, (what, errs)
+    return errs
+
+
+def _assert_dts(gdt, odt, tol=DT_TOL):
+    assert len(gdt) == len(odt)
+    rel = np.abs(np.asarray(gdt) - np.asarray(odt)) / np.abs(np.asarray(odt))
+    assert np.all(rel <= tol), rel
+
+
+# ---------------------------------------------------------------------------
+# the small configuration: 32^3 diagonal Riemann problem, outflow, 20 steps
+# ---------------------------------------------------------------------------
+
+def test_diagonal_32_host_dt_matches_oracle():
+    _say("case: diagonal_riemann 32^3 outflow, 20 steps, host dt")
+    U0 = wl.diagonal_riemann(32)
+    ref, odt = oracle_run(U0, "outflow", 20)
+    out, gdt = gpu_run_host_dt(U0, "outflow", 20)
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
+
+
+def test_diagonal_32_device_dt_matches_host_dt_bitwise():
+    _say("case: diagonal_riemann 32^3 outflow, 20 steps, device dt")
+    U0 = wl.diagonal_riemann(32)
+    a, adt = gpu_run_host_dt(U0, "outflow", 20)
+    b, bdt, t = gpu_run_device_dt(U0, "outflow", 20)
+    assert np.array_equal(adt, bdt)
+    assert np.array_equal(a, b)
+    assert t == pytest.approx(math.fsum(bdt), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# periodic cubes with both workloads of the per-GPU configuration, small
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["sine", "plane0", "plane1"])
+def test_periodic_64_matches_oracle(case):
+    n, steps = 64, 100
+    _say(f"case: {case} {n}^3 periodic, {steps} steps, device dt")
+    U0 = wl.sine_wave(n, n, n) if case == "sine" else wl.random_plane(n, n, n, seed=int(case[-1]))
+    ref, odt = oracle_run(U0, "periodic", steps)
+    out, gdt, _ = gpu_run_device_dt(U0, "periodic", steps)
+    _assert_dts(gdt, odt, tol=1e-13)
+    _assert_parity(out, ref)
+
+
+# ---------------------------------------------------------------------------
+# ragged and odd meshes, both boundary kinds, several launch shapes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+@pytest.mark.parametrize("shape", [(37, 20, 9), (5, 33, 17), (1, 1, 7), (64, 1, 1), (2, 2, 2),
+                                   (17, 16, 40)])
+def test_ragged_meshes_match_oracle(shape, bc):
+    nx, ny, nz = shape
+    _say(f"case: random_plane {shape} {bc}, 6 steps, host dt")
+    U0 = wl.random_plane(nx, ny, nz, seed=7)
+    ref, odt = oracle_run(U0, bc, 6)
+    out, gdt = gpu_run_host_dt(U0, bc, 6)
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
+
+
+@pytest.mark.parametrize("launch", [(16, 0), (8, 0), (16, 1), (8, 3), (16, 64), (8, 7)])
+def test_launch_shapes_give_identical_results(launch):
+    _say(f"case: random_plane (40,24,20) outflow, 5 steps, launch {launch}")
+    U0 = wl.random_plane(40, 24, 20, seed=11)
+    base, bdt = gpu_run_host_dt(U0, "outflow", 5, launch=(16, 0))
+    out, odt = gpu_run_host_dt(U0, "outflow", 5, launch=launch)
+    assert np.array_equal(bdt, odt)
+    assert np.array_equal(base, out)
+
+
+def test_repeated_runs_are_bitwise_identical():
+    _say("case: random_plane 48^3 periodic, 10 steps, twice")
+    U0 = wl.random_plane(48, 48, 48, seed=2)
+    a, adt, _ = gpu_run_device_dt(U0, "periodic", 10)
+    b, bdt, _ = gpu_run_device_dt(U0, "periodic", 10)
+    assert np.array_equal(adt, bdt)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_aligned_sod_to_end_time_matches_oracle(axis):
+    _say(f"case: sod axis {axis}, 64 x 4 x 4, t_end 0.1, device dt")
+    U0 = wl.sod(64, axis, 4)
+    ref, odt = oracle_run(U0, "outflow", 10000, t_end=0.1)
+    out, gdt, t = gpu_run_device_dt(U0, "outflow", len(odt) + 3, t_end=0.1)
+    # steps after the end time are exact no-ops (dt = 0)
+    assert np.all(gdt[len(odt):] == 0.0)
+    _assert_dts(gdt[:len(odt)], odt, tol=1e-13)
+    assert t == pytest.approx(0.1, abs=1e-15)
+    _assert_parity(out, ref)
+
+
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_uniform_state_stays_bitwise_uniform(bc):
+    _say(f"case: uniform (19, 18, 21) {bc}")
+    U0 = wl.uniform(19, 18, 21, rho=0.7, v=(0.3, -1.1, 0.25), p=2.5)
+    out, _ = gpu_run_host_dt(U0, bc, 5)
+    assert np.array_equal(out, U0)
+
+
+def test_periodic_conservation_on_gpu():
+    _say("case: random_plane 48^3 periodic conservation, 30 steps")
+    U0 = wl.random_plane(48, 48, 48, seed=4)
+    U0[1] += 0.3 * U0[0]
+    U0[4] += 0.045 * U0[0]
+    out, _, _ = gpu_run_device_dt(U0, "periodic", 30)
+    totals = [math.fsum(U0[f].ravel()) for f in range(5)]
+    scale = max(abs(t) for t in totals)
+    for f in range(5):
+        assert abs(math.fsum(out[f].ravel()) - totals[f]) <= 1e-13 * scale, f
+
+
+# ---------------------------------------------------------------------------
+# error paths (forced from the host; every kernel exits normally)
+# ---------------------------------------------------------------------------
+
+def test_nonphysical_input_is_reported_once():
+    from paper_1812_07977_amd import Fluid, NonPhysicalError
+    _say("case: negative density in one cell")
+    U0 = wl.uniform(16, 16, 16)
+    U0[0, 3, 4, 5] = -1.0
+    U = to_gpu(U0)
+    with Fluid((16, 16, 16)) as F:
+        with pytest.raises(NonPhysicalError):
+            F.dt(U)
+        F.sync()  # reported once, then cleared
+        F.step(U, 1e-3)
+        with pytest.raises(NonPhysicalError):
+            F.sync()
+
+
+def test_nan_energy_is_reported():
+    from paper_1812_07977_amd import Fluid, NonPhysicalError
+    _say("case: NaN energy in one cell")
+    U0 = wl.uniform(8, 9, 10)
+    U0[4, 9, 8, 7] = np.nan
+    U = to_gpu(U0)
+    with Fluid((8, 9, 10), bc="periodic") as F:
+        with pytest.raises(NonPhysicalError):
+            F.dt(U)
+
+
+def test_bad_arguments_raise_before_launch():
+    import torch
+    from paper_1812_07977_amd import Fluid, GSError
+    with Fluid((8, 8, 8)) as F:
+        U = to_gpu(wl.uniform(8, 8, 8))
+        with pytest.raises(GSError):
+            F.step(U, -1.0)
+        with pytest.raises(GSError):
+            F.step(U, float("nan"))
+        with pytest.raises(ValueError):
+            F.step(torch.zeros((5, 8, 8, 9), dtype=torch.float64, device="cuda"), 0.1)
+        with pytest.raises(TypeError):
+            F.step(U.float(), 0.1)
+        with pytest.raises(GSError):
+            F.set_launch(tile_y=5)
+        F.sync()
+
+
+def test_time_set_and_read():
+    from paper_1812_07977_amd import Fluid
+    U = to_gpu(wl.uniform(8, 8, 8))
+    with Fluid((8, 8, 8)) as F:
+        F.time = 0.25
+        assert F.time == 0.25
+        F.step(U, 0.125)
+        assert F.time == 0.375
+
+
+def test_profiling_counts_launches():
+    from paper_1812_07977_amd import Fluid
+    U = to_gpu(wl.sine_wave(32, 32, 32))
+    with Fluid((32, 32, 32), bc="periodic") as F:
+        F.profile(True)
+        F.advance(U, 3)
+        ms1, n1 = F.kernel_ms(0)
+        ms2, n2 = F.kernel_ms(1)
+        ms3, n3 = F.kernel_ms(2)
+        assert (n1, n2, n3) == (3, 3, 1)
+        assert ms1 > 0 and ms2 > 0 and ms3 > 0
+        assert F.kernel_ms(0) == (0.0, 0)
+
+
+# ---------------------------------------------------------------------------
+# full sizes, in the launch configuration of the benchmark (device dt)
+# ---------------------------------------------------------------------------
+
+def test_full_256_sine_matches_oracle_everywhere():
+    n, steps = 256, 2
+    _say(f"case: sine {n}^3 periodic, {steps} steps, full comparison")
+    U0 = wl.sine_wave(n, n, n)
+    out, gdt, _ = gpu_run_device_dt(U0, "periodic", steps)
+    ref, odt = oracle_run(U0, "periodic", steps)
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
+
+
+@pytest.mark.parametrize("case", ["sine", "plane0"])
+def test_full_512_sampled_windows_match_oracle(case):
+    n = 512
+    _say(f"case: {case} {n}^3 periodic, 1 step, sampled windows")
+    U0 = wl.sine_wave(n, n, n) if case == "sine" else wl.random_plane(n, n, n, seed=0)
+    out, gdt, _ = gpu_run_device_dt(U0, "periodic", 1)
+    h = 1.0 / n
+    dt = oracle.time_step(U0, (h, h, h), GAMMA, CFL)
+    _assert_dts(gdt, [dt])
+    rng = np.random.default_rng(123)
+    origins = [(0, 0, 0), (n - 3, n - 2, n - 4), (255, 256, 250)]
+    origins += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(5)]
+    size = (6, 5, 4)
+    scale = np.max(np.abs(U0), axis=(1, 2, 3))
+    for o in origins:
+        win = oracle.step_window(U0, (h, h, h), GAMMA, dt, o, size)
+        ii = [(o[0] + i) % n for i in range(size[0])]
+        jj = [(o[1] + j) % n for j in range(size[1])]
+        kk = [(o[2] + k) % n for k in range(size[2])]
+        g = out[:, kk][:, :, jj][:, :, :, ii]
+        for f in range(5):
+            s = scale[f] if scale[f] > 0 else np.max(scale)
+            assert np.max(np.abs(g[f] - win[f])) / s <= TOL, (o, f)
+
+
+def test_full_512_random_plane_conservation():
+    n = 512
+    _say(f"case: plane1 {n}^3 periodic, 3 steps, conservation")
+    U0 = wl.random_plane(n, n, n, seed=1)
+    import torch
+    U = to_gpu(U0)
+    before = U.sum(dim=(1, 2, 3)).cpu().numpy()
+    from paper_1812_07977_amd import Fluid
+    with Fluid((n, n, n), bc="periodic") as F:
+        F.advance(U, 3)
+        F.sync()
+    after = U.sum(dim=(1, 2, 3)).cpu().numpy()
+    scale = np.max(np.abs(before))
+    assert np.max(np.abs(after - before)) <= 1e-12 * scale
