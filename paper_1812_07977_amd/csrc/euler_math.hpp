@@ -21,26 +21,25 @@ struct Phys {
     double cfl;      // Courant number
 };
 
-// 1/a for a > 0 normal: hardware reciprocal estimate refined by two Newton
-// steps r <- r + r (1 - a r), each of which squares the relative error.
+// 1/a for a > 0 normal: the hardware estimate r (relative error below
+// 2^-24) refined by one third-order step r (1 + e + e^2), e = 1 - a r, which
+// cubes the error, leaving only the final rounding.
 __device__ __forceinline__ double recip(double a)
 {
     double r = __builtin_amdgcn_rcp(a);
     double e = __builtin_fma(-a, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-a, r, 1.0);
-    return __builtin_fma(r, e, r);
+    return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
-// 1/sqrt(x) for x > 0 normal: hardware estimate refined by two Newton steps
-// y <- y + (y/2)(1 - x y^2).
+// 1/sqrt(x) for x > 0 normal: the hardware estimate y (relative error below
+// 2^-24) refined by one third-order step y (1 + e/2 + 3e^2/8),
+// e = 1 - x y^2.
 __device__ __forceinline__ double rsqrt(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
     double e = __builtin_fma(-(x * y), y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-(x * y), y, 1.0);
-    return __builtin_fma(0.5 * y, e, y);
+    double q = e * __builtin_fma(e, 0.375, 0.5);
+    return __builtin_fma(y, q, y);
 }
 
 // Sound speed sqrt(gamma p / rho), written as (gamma p) / sqrt(gamma p rho)
@@ -98,8 +97,8 @@ __device__ __forceinline__ void hll_flux(const double L[NV], const double R[NV],
     // conserved face states
     double mL1 = L[0] * L[1], mL2 = L[0] * L[2], mL3 = L[0] * L[3];
     double mR1 = R[0] * R[1], mR2 = R[0] * R[2], mR3 = R[0] * R[3];
-    double v2L = (L[1] * L[1] + L[2] * L[2]) + L[3] * L[3];
-    double v2R = (R[1] * R[1] + R[2] * R[2]) + R[3] * R[3];
+    double v2L = __builtin_fma(L[3], L[3], __builtin_fma(L[2], L[2], L[1] * L[1]));
+    double v2R = __builtin_fma(R[3], R[3], __builtin_fma(R[2], R[2], R[1] * R[1]));
     double EL = __builtin_fma(L[4], k.inv_gm1, (0.5 * L[0]) * v2L);
     double ER = __builtin_fma(R[4], k.inv_gm1, (0.5 * R[0]) * v2R);
     const double uL[NV] = {L[0], mL1, mL2, mL3, EL};
@@ -116,13 +115,10 @@ __device__ __forceinline__ void hll_flux(const double L[NV], const double R[NV],
     double sl = __builtin_fmin(__builtin_fmin(unL - cL, unR - cR), 0.0);
     double sr = __builtin_fmax(__builtin_fmax(unL + cL, unR + cR), 0.0);
     double inv = recip(sr - sl);
-    double slsr = sl * sr;
+    double wl = sr * inv, wr = -sl * inv, wd = sl * wl;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double t = __builtin_fma(-sl, fR[v], sr * fL[v]);
-        t = __builtin_fma(slsr, uR[v] - uL[v], t);
-        F[v] = t * inv;
-    }
+    for (int v = 0; v < NV; ++v)
+        F[v] = __builtin_fma(wl, fL[v], __builtin_fma(wr, fR[v], wd * (uR[v] - uL[v])));
 }
 
 // Flux through the face between cells b and c along axis AX, from the

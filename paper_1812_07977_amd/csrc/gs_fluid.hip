@@ -160,8 +160,33 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     if (halo)
         hoff = map_index(y0 + hyl, g.ny, g.periodic) * g.nx + map_index(x0 + hxl, g.nx, g.periodic);
 
-    // edge-face role: the last TX + TY threads
+    // edge-face role: the last TX + TY threads compute the faces on the far
+    // edges of the tile, y-faces above row TY-1 (e < TX) and x-faces right of
+    // column TX-1.  Both are evaluated as y-faces: for an x-face the two
+    // tangential velocity components are exchanged through the LDS addressing
+    // (and exchanged back on the way out), which yields bit-identical values
+    // since every sum and product involved is commutative.
     const int e = tid - (NT - (TX + TY));
+    constexpr int PLW = WY * WX;               // one field of Ws
+    constexpr int PFX = TY * (TX + 1), PFY = (TY + 1) * TX;
+    int e_base = 0, e_step = 0, e_v1 = PLW, e_v2 = 2 * PLW;
+    double* e_out = nullptr;
+    int e_f1 = PFY, e_f2 = 2 * PFY, e_fs = PFY;
+    if (e >= 0 && e < TX) {
+        e_base = TY * WX + e + 2;
+        e_step = WX;
+        e_out = &Fy[0][TY][e];
+    } else if (e >= TX) {
+        const int r = e - TX;
+        e_base = (r + 2) * WX + TX;
+        e_step = 1;
+        e_v1 = 2 * PLW;
+        e_v2 = PLW;
+        e_out = &Fx[0][r][TX];
+        e_f1 = 2 * PFX;
+        e_f2 = PFX;
+        e_fs = PFX;
+    }
 
     // time step
     double dt = dt_host;
@@ -190,46 +215,34 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
 
     // ---- prologue: planes z0-2 .. z0+2 of the own column, halo of z0 ----
     double Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
-    double WLz[NV], Fm[NV];
+    double Wk[NV], Wk1[NV], WLz[NV], Fm[NV];
     {
-        double Um2[NV], Um1[NV];
+        double Um2[NV], Um1[NV], Wm2[NV], Wm1[NV];
         load5(plane_ptr(Uin, z0 - 2), F, own, Um2);
         load5(plane_ptr(Uin, z0 - 1), F, own, Um1);
         load5(plane_ptr(Uin, z0), F, own, Uk);
         load5(plane_ptr(Uin, z0 + 1), F, own, Uk1);
         load5(plane_ptr(Uin, z0 + 2), F, own, Uk2);
         if (halo) load5(plane_ptr(Uin, z0), F, hoff, Hk);
-        double Wm2[NV], Wm1[NV], W0[NV], W1[NV];
         bad |= !cons_to_prim(Um2, Wm2, k);
         bad |= !cons_to_prim(Um1, Wm1, k);
-        bad |= !cons_to_prim(Uk, W0, k);
-        bad |= !cons_to_prim(Uk1, W1, k);
-        face_flux<2>(Wm2, Wm1, W0, W1, k, Fm);  // face z0 - 1/2
-        double Wp2[NV];
-        bad |= !cons_to_prim(Uk2, Wp2, k);
+        bad |= !cons_to_prim(Uk, Wk, k);
+        bad |= !cons_to_prim(Uk1, Wk1, k);
+        face_flux<2>(Wm2, Wm1, Wk, Wk1, k, Fm);  // face z0 - 1/2
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            WLz[v] = __builtin_fma(0.5, minmod(W0[v] - Wm1[v], W1[v] - W0[v]), W0[v]);
+            WLz[v] = __builtin_fma(0.5, minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
     }
 
     for (int z = z0; z < z1; ++z) {
-        // prefetch plane z+3 of the own column and the halo of plane z+1
-        double Uk3[NV], Hk1[NV], Uo[NV];
-        load5(plane_ptr(Uin, z + 3), F, own, Uk3);
-        if (halo) load5(plane_ptr(Uin, z + 1), F, hoff, Hk1);
-        if (STAGE == 2) load5(Un + (long long)z * g.plane, F, own, Uo);
-
         // stage the plane's primitives in LDS
-        {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = Wk[v];
+        if (halo) {
             double w[NV];
-            cons_to_prim(Uk, w, k);
+            cons_to_prim(Hk, w, k);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = w[v];
-            if (halo) {
-                cons_to_prim(Hk, w, k);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
-            }
+            for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
         }
         __syncthreads();
 
@@ -256,52 +269,53 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fy[v][ty][tx] = f[v];
         }
-        // faces on the far edges of the tile
+        // faces on the far edges of the tile (one evaluation per lane)
         if (e >= 0) {
+            const double* ws = &Ws[0][0][0];
+            const int off[NV] = {0, e_v1, e_v2, 3 * PLW, 4 * PLW};
             double a[NV], b[NV], c[NV], d[NV], f[NV];
-            if (e < TX) {  // y-face between rows TY-1 and TY, column e
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    a[v] = Ws[v][TY][e + 2];
-                    b[v] = Ws[v][TY + 1][e + 2];
-                    c[v] = Ws[v][TY + 2][e + 2];
-                    d[v] = Ws[v][TY + 3][e + 2];
-                }
-                face_flux<1>(a, b, c, d, k, f);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Fy[v][TY][e] = f[v];
-            } else {       // x-face between columns TX-1 and TX, row e - TX
-                const int r = e - TX;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    a[v] = Ws[v][r + 2][TX];
-                    b[v] = Ws[v][r + 2][TX + 1];
-                    c[v] = Ws[v][r + 2][TX + 2];
-                    d[v] = Ws[v][r + 2][TX + 3];
-                }
-                face_flux<0>(a, b, c, d, k, f);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Fx[v][r][TX] = f[v];
+            for (int v = 0; v < NV; ++v) {
+                const double* p = ws + off[v] + e_base;
+                a[v] = p[0];
+                b[v] = p[e_step];
+                c[v] = p[2 * e_step];
+                d[v] = p[3 * e_step];
             }
+            face_flux<1>(a, b, c, d, k, f);
+            e_out[0] = f[0];
+            e_out[e_f1] = f[1];
+            e_out[e_f2] = f[2];
+            e_out[3 * e_fs] = f[3];
+            e_out[4 * e_fs] = f[4];
         }
         __syncthreads();
 
+        // prefetch plane z+3 of the own column and the halo of plane z+1
+        // (both consumed one iteration later)
+        double Uk3[NV], Uo[NV];
+        load5(plane_ptr(Uin, z + 3), F, own, Uk3);
+        if (halo) load5(plane_ptr(Uin, z + 1), F, hoff, Hk);
+
         // z-face above the own cell, from the register queue
-        double Fp[NV], WLn[NV];
+        double Fp[NV], W2[NV];
         {
-            double W0[NV], W1[NV], W2[NV], R[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) W0[v] = Ws[v][ty + 2][tx + 2];
-            cons_to_prim(Uk1, W1, k);
+            double R[NV];
             bad |= !cons_to_prim(Uk2, W2, k);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double d1 = W1[v] - W0[v], d2 = W2[v] - W1[v];
-                double s1 = minmod(d1, d2);
-                R[v] = __builtin_fma(-0.5, s1, W1[v]);
-                WLn[v] = __builtin_fma(0.5, s1, W1[v]);
+                const double w0 = Ws[v][ty + 2][tx + 2];
+                double s1 = minmod(Wk1[v] - w0, W2[v] - Wk1[v]);
+                R[v] = __builtin_fma(-0.5, s1, Wk1[v]);
+                Wk[v] = __builtin_fma(0.5, s1, Wk1[v]);  // left state of face z+3/2
             }
             hll_flux<2>(WLz, R, k, Fp);
+        }
+        if (STAGE == 2) {
+            // keep this load after the z-face flux: it is the last value the
+            // combine needs, and hoisting it raises register pressure
+            __builtin_amdgcn_sched_barrier(0);
+            load5(Un + (long long)z * g.plane, F, own, Uo);
         }
 
         // divergence, RK combine, store
@@ -330,14 +344,15 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
             }
         }
 
-        // rotate the queue
+        // rotate the queue: Wk holds the new left z-face state until here
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+            WLz[v] = Wk[v];
+            Wk[v] = Wk1[v];
+            Wk1[v] = W2[v];
             Uk[v] = Uk1[v];
             Uk1[v] = Uk2[v];
             Uk2[v] = Uk3[v];
-            Hk[v] = Hk1[v];
-            WLz[v] = WLn[v];
             Fm[v] = Fp[v];
         }
     }
