@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# FP64 vector peak 78.6 TFLOP/s counts an FMA as 2 flops: 256 CUs x 64 FP64
+# lanes per clock x 2.4 GHz = 39.3 T lane operations per second, the issue
+# rate of one wave64 VALU instruction per SIMD per 4 clocks
+VALU_LANE_OPS_PEAK_T = 39.3
 BYTES_PER_CELL = {0: 80.0,     # substep 1: read U(n), write U(1)
                   1: 120.0,    # substep 2: read U(1) and U(n), write U(n+1)
                   2: 40.0}     # dt reduction: read U
@@ -44,17 +48,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, size, case):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_stage_kernels_{size}cubed_{case}.md")
+def profile_figure(key, size, case):
+    """A per-launch figure from the committed rocprofv3 counter summary of
+    the stage kernels, if it was taken on the current kernel source; else
+    None (the counters no longer describe the code)."""
+    path = os.path.join(ROOT, "profiles", f"counters_stage_kernels_{size}cubed_{case}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"^source_sha256_16:\s*(\w+)", text, re.M)
     if not m or m.group(1) != source_hash():
         return None
-    m = re.search(rf"^bytes_per_launch_kernel{kernel}:\s*([0-9.eE+]+)", text, re.M)
+    m = re.search(rf"^{key}:\s*([0-9.eE+]+)", text, re.M)
     return float(m.group(1)) if m else None
 
 
@@ -65,7 +70,7 @@ def make_input(size, case):
     return wl.random_plane(size, size, size, seed=0)
 
 
-def cpu_baseline(case, size=256, steps=1):
+def cpu_baseline(case, size=256, steps=10):
     """The oracle as it stands, on a bounded sample: the same case on a
     size^3 mesh for `steps` RK2 steps, using every host core OpenMP gives it."""
     import oracle
@@ -113,10 +118,12 @@ def main():
     F.set_launch(args.tile_y, args.chunk_z)
 
     if args.copy_probe:
+        # a plain streaming kernel of known size for scaling HBM counters:
+        # an elementwise negation reads copy_probe MiB and writes as many
         nb = args.copy_probe * 1024 * 1024 // 8
         a = torch.ones(nb, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -151,12 +158,23 @@ def main():
     ms_sum, launches = per_kernel[dom]
     avg_s = ms_sum / launches / 1e3
     achieved = BYTES_PER_CELL[dom] * cells / avg_s / 1e9
-    traffic = measured_traffic(dom, n, args.case)
+    traffic = profile_figure(f"hbm_bytes_per_launch_kernel{dom}", n, args.case)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": KERNEL_NAMES[dom],
                 "avg_launch_ms": round(avg_s * 1e3, 4),
                 "bytes_per_launch": BYTES_PER_CELL[dom] * cells}
+    # the same kernel against the vector ALU: VALU lane operations per launch
+    # (wave64 VALU instructions counted by rocprofv3, x64) over the same
+    # duration, against the issue peak of one wave64 instruction per SIMD per
+    # 4 clocks
+    valu = profile_figure(f"valu_lane_ops_per_launch_kernel{dom}", n, args.case)
+    alu = None
+    if valu is not None:
+        a_t = valu / avg_s / 1e12
+        alu = {"bound": "alu", "achieved": round(a_t, 2), "peak": VALU_LANE_OPS_PEAK_T,
+               "unit": "T VALU lane-ops/s", "frac": round(a_t / VALU_LANE_OPS_PEAK_T, 4),
+               "ops_per_launch": valu}
 
     line = {
         "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1,
@@ -171,6 +189,7 @@ def main():
                               for k, v in per_kernel.items()},
         "sim_time": t_sim,
         "roofline": roofline,
+        "alu": alu,
         "context": "paper: ~12X wall-time speedup of one V100 over 7 Power9 cores "
                    "(Summit, 256^3 per rank, incl. host transfers)",
     }
