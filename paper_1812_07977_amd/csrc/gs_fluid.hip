@@ -127,6 +127,8 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     __shared__ double Ws[NV][WY][WX];     // primitives of the plane, +2 halo
     __shared__ double Fx[NV][TY][TX + 1]; // x-face fluxes, face i-1/2 at [i]
     __shared__ double Fy[NV][TY + 1][TX]; // y-face fluxes, face j-1/2 at [j]
+    constexpr int NH = 4 * (TX + TY);     // halo cells of one plane
+    __shared__ double Hr[3][NV][NH];      // halo ring: raw states of 3 planes
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -142,7 +144,12 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     const bool active = (i < g.nx) & (j < g.ny);
     const int own = map_index(j, g.ny, g.periodic) * g.nx + map_index(i, g.nx, g.periodic);
 
-    // halo role: 4 cells per tile row (x) and per tile column (y)
+    // halo role: 4 cells per tile row (x) and per tile column (y).  Halo
+    // thread h loads its cell of plane z+3 in the iteration of plane z, at
+    // the same time as the neighbouring tiles load that plane as their own
+    // columns, so the shared cache lines are fetched from HBM once; the raw
+    // values wait in the thread's own slots of the LDS ring Hr until the
+    // plane is staged (no other thread touches those slots).
     int hxl = 0, hyl = 0, hoff = 0;
     bool halo = false;
     if (tid < 4 * TY) {
@@ -215,6 +222,7 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
 
     // ---- prologue: planes z0-2 .. z0+2 of the own column, halo of z0 ----
     double Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
+    const int hslot = halo ? tid : 0;
     double Wk[NV], Wk1[NV], WLz[NV], Fm[NV];
     {
         double Um2[NV], Um1[NV], Wm2[NV], Wm1[NV];
@@ -223,7 +231,17 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
         load5(plane_ptr(Uin, z0), F, own, Uk);
         load5(plane_ptr(Uin, z0 + 1), F, own, Uk1);
         load5(plane_ptr(Uin, z0 + 2), F, own, Uk2);
-        if (halo) load5(plane_ptr(Uin, z0), F, hoff, Hk);
+        if (halo) {
+            // ring: planes z0, z0+1 stored, z0+2 held in registers
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double h[NV];
+                load5(plane_ptr(Uin, z0 + q), F, hoff, h);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Hr[(z0 + q) % 3][v][hslot] = h[v];
+            }
+            load5(plane_ptr(Uin, z0 + 2), F, hoff, Hk);
+        }
         bad |= !cons_to_prim(Um2, Wm2, k);
         bad |= !cons_to_prim(Um1, Wm1, k);
         bad |= !cons_to_prim(Uk, Wk, k);
@@ -234,13 +252,22 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
             WLz[v] = __builtin_fma(0.5, minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
     }
 
+    double Uon[NV];  // U(n) of the next plane (stage 2), prefetched
+    if (STAGE == 2) load5(Un + (long long)z0 * g.plane, F, own, Uon);
+
     for (int z = z0; z < z1; ++z) {
         // stage the plane's primitives in LDS
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = Wk[v];
         if (halo) {
             double w[NV];
-            cons_to_prim(Hk, w, k);
+            double h[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Hr[(z + 2) % 3][v][hslot] = Hk[v];   // plane z+2, loaded last iteration
+                h[v] = Hr[z % 3][v][hslot];           // plane z
+            }
+            cons_to_prim(h, w, k);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
         }
@@ -291,11 +318,16 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
         }
         __syncthreads();
 
-        // prefetch plane z+3 of the own column and the halo of plane z+1
-        // (both consumed one iteration later)
+        // prefetch plane z+3 of the own column and of the halo, and U(n) of
+        // the next plane (stage 2)
         double Uk3[NV], Uo[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
-        if (halo) load5(plane_ptr(Uin, z + 1), F, hoff, Hk);
+        if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
+        if (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Uo[v] = Uon[v];
+            if (z + 1 < z1) load5(Un + (long long)(z + 1) * g.plane, F, own, Uon);
+        }
 
         // z-face above the own cell, from the register queue
         double Fp[NV], W2[NV];
@@ -310,12 +342,6 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
                 Wk[v] = __builtin_fma(0.5, s1, Wk1[v]);  // left state of face z+3/2
             }
             hll_flux<2>(WLz, R, k, Fp);
-        }
-        if (STAGE == 2) {
-            // keep this load after the z-face flux: it is the last value the
-            // combine needs, and hoisting it raises register pressure
-            __builtin_amdgcn_sched_barrier(0);
-            load5(Un + (long long)z * g.plane, F, own, Uo);
         }
 
         // divergence, RK combine, store
@@ -515,10 +541,13 @@ Launch make_launch(const gs_fluid* h)
     const int ntile = g.ntx * g.nty;
     int kz = h->chunk_z;
     if (kz <= 0) {
-        // aim for about 2048 workgroups (several per CU slot), chunks of at
-        // least 8 planes
+        // aim for at least 2048 workgroups (several per CU slot) with chunks
+        // of 8 to 64 planes: shorter chunks keep the workgroups that share
+        // halo lines closer together in z (fewer L2 misses), longer ones
+        // waste less on the 4 planes each chunk re-reads
         long long want_chunks = (2048 + ntile - 1) / ntile;
         kz = (int)((h->nz + want_chunks - 1) / want_chunks);
+        if (kz > 64) kz = 64;
         if (kz < 8) kz = 8;
     }
     if (kz > h->nz) kz = h->nz;
