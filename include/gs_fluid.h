@@ -78,7 +78,7 @@ enum {
  * gs_fluid_destroy.  On success *out is the handle; on failure *out is NULL
  * and gs_fluid_last_error(NULL) gives the reason.  Paper: persistent
  * device allocation at initialisation (Section 2.1, AllocateDevice), one
- * device per process (Section 2.2).
+ * device per process (Section 1; the default device of Section 2.2).
  */
 int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz,
                     double gamma, double cfl, int bc, int dtype, void* stream,

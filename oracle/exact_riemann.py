@@ -2,7 +2,7 @@
 
 Part of the test infrastructure: the oracle's scheme is checked against it on
 grid-aligned shock-tube problems such as Sod's, which the paper's Riemann
-problem extends to 3D (Section 4).  The solution is the classical one: the
+problem extends to 3D (Section 3).  The solution is the classical one: the
 star-region pressure p* is the root of
 
     f(p) = f_L(p) + f_R(p) + (u_R - u_L) = 0,

@@ -1,6 +1,6 @@
 """Pins of the oracle's whole RK2 step against what the physics fixes.
 
-- Sod's tube (the paper's Riemann problem is its 3D extension, Section 4)
+- Sod's tube (the paper's Riemann problem is its 3D extension, Section 3)
   against the exact solution, aligned with each axis;
 - a uniform state stays bitwise uniform (every face sees identical inputs);
 - periodic meshes conserve mass, momentum and energy to round-off;

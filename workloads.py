@@ -12,7 +12,8 @@ mesh spans the unit cube; cell (i, j, k) has centre ((i+1/2)h, (j+1/2)h,
 for the left state); smooth data are exact cell averages.
 
 Workloads (the paper's problem is a 3D extension of Sod's shock tube evolved
-to t = 0.25, Section 4; the perf runs use 256^3 cells per GPU):
+to t = 0.25, Section 3; its performance runs use 256^3 cells per GPU,
+Section 4):
   diagonal_riemann   32^3 outflow problem: left state where x+y+z < 1.5
   sod                grid-aligned Sod tube along one axis
   sine_wave          smooth density wave advected at uniform v, p
