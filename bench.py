@@ -1,7 +1,9 @@
-"""Benchmark: FP64 RK2 finite-volume Euler steps per second on one MI355X.
+"""Benchmark: FP64 RK2 finite-volume Euler steps per second on one MI355X,
+and the compensated FP32 form beside it.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--size 512]
-                    [--case sine|plane] [--no-cpu-baseline] [--copy-probe MIB]
+                    [--case sine|plane] [--no-cpu-baseline] [--no-forms]
+                    [--copy-probe MIB]
 
 A step is one RK2 step of the whole hot path on the periodic cube: the two
 fused substep kernels, with the CFL max-reduction fused into the second one
@@ -13,7 +15,11 @@ starts: the smooth case rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (1,1,1), p = 1
 Prints one JSON line with the cell-update rate, the roofline of the dominant
 kernel (per-launch algorithmic HBM bytes over its average event-timed
 duration, against the 8 TB/s HBM3E peak) and the CPU oracle timed on a
-bounded sample on the host cores.
+bounded sample on the host cores.  Under "forms" the FP32 form is timed the
+same way on the same input, with its speedup over FP64 and its L1 and
+L-infinity error per field against the FP64 solution of the same input after
+the same steps (the FP32 run is driven with the FP64 run's time steps; the
+FP64 path itself matches the CPU oracle to 1e-12).
 """
 import argparse
 import hashlib
@@ -31,9 +37,16 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # lanes per clock x 2.4 GHz = 39.3 T lane operations per second, the issue
 # rate of one wave64 VALU instruction per SIMD per 4 clocks
 VALU_LANE_OPS_PEAK_T = 39.3
-BYTES_PER_CELL = {0: 80.0,     # substep 1: read U(n), write U(1)
-                  1: 120.0,    # substep 2: read U(1) and U(n), write U(n+1)
-                  2: 40.0}     # dt reduction: read U
+# algorithmic HBM bytes per cell and launch
+BYTES_PER_CELL = {
+    "f64": {0: 80.0,     # substep 1: read U(n), write U(1)
+            1: 120.0,    # substep 2: read U(1) and U(n), write U(n+1)
+            2: 40.0},    # dt reduction: read U
+    "f32": {0: 60.0,     # substep 1: read U(n), write U(1) and dU(U(n))
+            1: 120.0,    # substep 2: read U(1), dU(U(n)), U(n) and its
+                         # compensation; write U(n+1) and its compensation
+            2: 20.0},    # dt reduction: read the head
+}
 KERNEL_NAMES = {0: "stage_kernel<1> (substep 1)", 1: "stage_kernel<2> (substep 2 + dt max)",
                 2: "rate reduction"}
 METRIC = "cell-updates/s per RK2 step & HBM GB/s; plain FP64 vs chosen forms @ L1 err"
@@ -48,11 +61,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def profile_figure(key, size, case):
+def profile_figure(key, size, case, dtype="f64"):
     """A per-launch figure from the committed rocprofv3 counter summary of
     the stage kernels, if it was taken on the current kernel source; else
     None (the counters no longer describe the code)."""
-    path = os.path.join(ROOT, "profiles", f"counters_stage_kernels_{size}cubed_{case}.md")
+    tag = "" if dtype == "f64" else "_" + dtype
+    path = os.path.join(ROOT, "profiles", f"counters_stage_kernels_{size}cubed_{case}{tag}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -86,6 +100,94 @@ def cpu_baseline(case, size=256, steps=10):
                       f"{el:.1f} s wall"}
 
 
+def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z):
+    """Warm-up and timed gs_fluid_advance runs of one form from U0; returns
+    the figures and the dt of every step (warm-up first)."""
+    import torch
+    from paper_1812_07977_amd import Fluid
+    F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic", dtype=dtype)
+    F.set_launch(tile_y, chunk_z)
+    S = F.state_from(U0)
+    log_w = torch.zeros(max(warmup, 1), dtype=torch.float64, device="cuda")
+    log_t = torch.zeros(max(steps, 1), dtype=torch.float64, device="cuda")
+    if warmup:
+        F.advance(S, warmup, 0.0, log_w)
+    F.sync()
+    F.profile(True)
+    for k in range(3):
+        F.kernel_ms(k)          # discard warm-up events
+
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    F.advance(S, steps, 0.0, log_t)
+    t1.record(stream)
+    F.sync()
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    per_kernel = {k: F.kernel_ms(k) for k in range(3)}
+    t_sim = F.time
+    result = F.to_f64(S) if dtype == "f64" else None
+    F.close()
+    dts = torch.cat([log_w[:warmup], log_t[:steps]]).cpu().numpy()
+    return {"total_ms": total_ms, "per_kernel": per_kernel, "t_sim": t_sim}, dts, result
+
+
+def roofline(dtype, n, case, per_kernel):
+    cells = n ** 3
+    dom = max((0, 1), key=lambda k: per_kernel[k][0])
+    ms_sum, launches = per_kernel[dom]
+    avg_s = ms_sum / launches / 1e3
+    bpc = BYTES_PER_CELL[dtype][dom]
+    achieved = bpc * cells / avg_s / 1e9
+    traffic = profile_figure(f"hbm_bytes_per_launch_kernel{dom}", n, case, dtype)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": KERNEL_NAMES[dom],
+            "avg_launch_ms": round(avg_s * 1e3, 4),
+            "bytes_per_launch": bpc * cells}
+    # the same kernel against the vector ALU: VALU lane operations per launch
+    # (wave64 VALU instructions counted by rocprofv3, x64) over the same
+    # duration, against the issue peak of one wave64 instruction per SIMD per
+    # 4 clocks
+    valu = profile_figure(f"valu_lane_ops_per_launch_kernel{dom}", n, case, dtype)
+    alu = None
+    if valu is not None:
+        a_t = valu / avg_s / 1e12
+        alu = {"bound": "alu", "achieved": round(a_t, 2), "peak": VALU_LANE_OPS_PEAK_T,
+               "unit": "T VALU lane-ops/s", "frac": round(a_t / VALU_LANE_OPS_PEAK_T, 4),
+               "ops_per_launch": valu}
+    return roof, alu
+
+
+def f32_error(U0, n, dts, U64):
+    """The FP32 form driven with the FP64 run's time steps from the same
+    input: relative L1 and L-infinity error per field against the FP64
+    result U64 (device)."""
+    import torch
+    from paper_1812_07977_amd import Fluid
+    F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic", dtype="f32")
+    S = F.state_from(U0)
+    for dt in dts:
+        F.step(S, float(dt))
+    F.sync()
+    U32 = F.to_f64(S)
+    F.close()
+    del S
+    l1, linf = [], []
+    for f in range(5):
+        d = (U32[f] - U64[f]).abs()
+        ref = U64[f].abs()
+        s1, sinf = float(ref.sum()), float(ref.max())
+        if sinf == 0.0:
+            s1, sinf = float(U64.abs().sum()) / 5, float(U64.abs().max())
+        l1.append(float(f"{float(d.sum()) / s1:.3e}"))
+        linf.append(float(f"{float(d.max()) / sinf:.3e}"))
+    return l1, linf
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +198,7 @@ def main():
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--chunk-z", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="time the FP64 form only")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -106,16 +209,11 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1812_07977_amd import Fluid
 
     n = args.size
     print(f"bench: {args.case} {n}^3 periodic, FP64, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     U0 = make_input(n, args.case)
-    U = torch.from_numpy(U0).to("cuda")
-    del U0
-    F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic")
-    F.set_launch(args.tile_y, args.chunk_z)
 
     if args.copy_probe:
         # a plain streaming kernel of known size for scaling HBM counters:
@@ -127,54 +225,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    if args.warmup:
-        F.advance(U, args.warmup)
-    F.sync()
-    F.profile(True)
-    for k in range(3):
-        F.kernel_ms(k)          # discard warm-up events
-
-    stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    F.advance(U, args.steps)
-    t1.record(stream)
-    F.sync()
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    per_kernel = {k: F.kernel_ms(k) for k in range(3)}
-    t_sim = F.time
-    F.close()
+    r64, dts64, U64 = timed_run(U0, n, "f64", args.steps, args.warmup, args.tile_y, args.chunk_z)
 
     cells = n ** 3
-    ms_per_step = total_ms / args.steps
-    rate = cells * args.steps / (total_ms / 1e3)
+    ms_per_step = r64["total_ms"] / args.steps
+    rate = cells * args.steps / (r64["total_ms"] / 1e3)
     alg_bytes_step = 200.0 * cells + 40.0 * cells / args.steps
-
-    # dominant kernel: the one with the largest total time
-    dom = max((0, 1), key=lambda k: per_kernel[k][0])
-    ms_sum, launches = per_kernel[dom]
-    avg_s = ms_sum / launches / 1e3
-    achieved = BYTES_PER_CELL[dom] * cells / avg_s / 1e9
-    traffic = profile_figure(f"hbm_bytes_per_launch_kernel{dom}", n, args.case)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": KERNEL_NAMES[dom],
-                "avg_launch_ms": round(avg_s * 1e3, 4),
-                "bytes_per_launch": BYTES_PER_CELL[dom] * cells}
-    # the same kernel against the vector ALU: VALU lane operations per launch
-    # (wave64 VALU instructions counted by rocprofv3, x64) over the same
-    # duration, against the issue peak of one wave64 instruction per SIMD per
-    # 4 clocks
-    valu = profile_figure(f"valu_lane_ops_per_launch_kernel{dom}", n, args.case)
-    alu = None
-    if valu is not None:
-        a_t = valu / avg_s / 1e12
-        alu = {"bound": "alu", "achieved": round(a_t, 2), "peak": VALU_LANE_OPS_PEAK_T,
-               "unit": "T VALU lane-ops/s", "frac": round(a_t / VALU_LANE_OPS_PEAK_T, 4),
-               "ops_per_launch": valu}
+    roof, alu = roofline("f64", n, args.case, r64["per_kernel"])
 
     line = {
         "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1,
@@ -186,13 +243,35 @@ def main():
                    "gamma": 1.4, "cfl": 0.5, "bc": "periodic"},
         "hbm_gbs_algorithmic": round(alg_bytes_step / (ms_per_step / 1e3) / 1e9, 1),
         "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
-                              for k, v in per_kernel.items()},
-        "sim_time": t_sim,
-        "roofline": roofline,
+                              for k, v in r64["per_kernel"].items()},
+        "sim_time": r64["t_sim"],
+        "roofline": roof,
         "alu": alu,
         "context": "paper: ~12X wall-time speedup of one V100 over 7 Power9 cores "
                    "(Summit, 256^3 per rank, incl. host transfers)",
     }
+
+    if not args.no_forms:
+        print("bench: FP32 form", file=sys.stderr, flush=True)
+        r32, _, _ = timed_run(U0, n, "f32", args.steps, args.warmup, args.tile_y, args.chunk_z)
+        ms32 = r32["total_ms"] / args.steps
+        roof32, alu32 = roofline("f32", n, args.case, r32["per_kernel"])
+        print("bench: FP32 form error against FP64", file=sys.stderr, flush=True)
+        l1, linf = f32_error(U0, n, dts64, U64)
+        line["forms"] = {"f32": {
+            "value": cells * args.steps / (r32["total_ms"] / 1e3), "unit": "cell-updates/s",
+            "ms_per_step": ms32, "speedup_vs_f64": round(ms_per_step / ms32, 3),
+            "dtype": "f32 state and flux arithmetic; f64 primitive recovery, dt, totals",
+            "hbm_gbs_algorithmic": round((180.0 * cells + 20.0 * cells / args.steps)
+                                         / (ms32 / 1e3) / 1e9, 1),
+            "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
+                                  for k, v in r32["per_kernel"].items()},
+            "l1_rel_err": l1, "linf_rel_err": linf,
+            "error_vs": f"FP64 solution of the same input after the same {args.warmup + args.steps} "
+                        "steps (same dt sequence)",
+            "roofline": roof32, "alu": alu32}}
+    del U64
+
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.case)

@@ -1,7 +1,7 @@
 /*
  * gs_fluid.h -- C ABI of libgs_fluid.so: one explicit RK2 finite-volume step
  * of the 3D ideal-gas Euler equations on a Cartesian mesh, as hand-written
- * HIP kernels for AMD gfx950 (MI355X), FP64.
+ * HIP kernels for AMD gfx950 (MI355X), in FP64 or in a compensated FP32 form.
  *
  * The step is the paper's "Fluid Evolution" loop body (Section 3, Algorithms
  * 1 and 2): ComputeTimeStep, then two substeps of ComputeDifferences,
@@ -10,7 +10,7 @@
  *     U(n+1) = 0.5 * (U(n) + U(1) + dU(U(1))),
  * with GhostExchange supplying two ghost layers per side before each
  * substep.  The paper names these kernels without formulas; this library
- * computes, in FP64:
+ * computes (FP64 form; the FP32 form below differs only in precision):
  *   - primitive recovery v = m/rho, p = (gamma-1)(E - m.v/2);
  *   - differences of primitives (index ranges of the paper's listing in
  *     Section 3) limited by minmod into slopes sigma; face states
@@ -22,7 +22,7 @@
  *   - ghost layers: outflow repeats the edge cell, periodic wraps.  The
  *     ghosts are virtual (index arithmetic); arrays hold proper cells only.
  *
- * Data layout.  A state U is one contiguous device array of doubles
+ * Data layout.  An FP64 state U is one contiguous device array of doubles
  * [5][nz][ny][nx], x fastest, fields (rho, m_x, m_y, m_z, E) -- the paper's
  * StorageForm Value(cell, field) with cells contiguous per field (Section
  * 2.1).  Pointers must be device pointers (hipMalloc or a PyTorch tensor's
@@ -30,10 +30,25 @@
  * was current at gs_fluid_create.  The caller owns U and keeps it alive until
  * the work queued on the handle's stream has finished.
  *
+ * FP32 form (dtype GS_F32).  The state is FP32 and the reconstruction and
+ * flux arithmetic runs in FP32; primitive recovery (where p = (gamma-1)(E -
+ * m.v/2) cancels when the kinetic energy dominates), signal rates, the time
+ * step, the device time and conserved totals are FP64.  The first substep
+ * keeps its increment dU(U(n)) in the workspace beside U(1), and the second
+ * adds 0.5 (dU(U(n)) + dU(U(1))) to U(n) by Kahan summation, so that
+ * increments below the rounding of U are not lost.  A state is therefore a
+ * pair: U points to 2 x 5 x nz x ny x nx floats,
+ * the head [5][nz][ny][nx] followed by the compensation [5][nz][ny][nx], and
+ * represents head - compensation (exact in FP64).  The kernels read the head
+ * as the cell values; only the RK combine reads and rewrites the
+ * compensation.  Start from compensation = 0, or from the FP32 rounding of
+ * head - u for FP64 initial data u, which the pair then holds to about 48
+ * bits.  Pointers must be aligned to 4 bytes (256 recommended).
+ *
  * Streams and synchronisation.  Every call queues work on the handle's
  * stream (hipStream_t, NULL = the legacy default stream) and returns without
- * waiting, except gs_fluid_dt, gs_fluid_sync, gs_fluid_get_time and
- * gs_fluid_kernel_ms, which wait for the stream.  A handle is not
+ * waiting, except gs_fluid_dt, gs_fluid_totals, gs_fluid_sync,
+ * gs_fluid_get_time and gs_fluid_kernel_ms, which wait for the stream.  A handle is not
  * thread-safe: use one handle per stream.
  *
  * Errors.  Every int-returning call returns GS_OK or a negative status;
@@ -57,8 +72,8 @@ typedef struct gs_fluid gs_fluid;
 /* Boundary kinds (GhostExchange on the physical boundary). */
 enum { GS_BC_OUTFLOW = 0, GS_BC_PERIODIC = 1 };
 
-/* Arithmetic types of the state.  Only FP64 is built. */
-enum { GS_F64 = 0 };
+/* Arithmetic types of the state: FP64, or the compensated FP32 form. */
+enum { GS_F64 = 0, GS_F32 = 1 };
 
 /* Status codes. */
 enum {
@@ -72,9 +87,11 @@ enum {
 /*
  * Create a solver for an nx*ny*nz mesh of proper cells with widths dx, dy,
  * dz, ratio of specific heats gamma (> 1), Courant number cfl (0 < cfl <= 1)
- * and boundary kind bc, on the current HIP device.  stream is a hipStream_t
- * or NULL.  Allocates the handle's workspace: one state array (the first
- * substep's result U(1)) plus a few kilobytes; the handle owns it until
+ * and boundary kind bc, on the current HIP device, for states of type dtype
+ * (GS_F64 or GS_F32).  stream is a hipStream_t or NULL.  Allocates the
+ * handle's workspace: the first substep's result U(1) (FP32 form: with its
+ * increment, 2 x 5 x nz x ny x nx floats) plus about 100 KB of reduction
+ * words; the handle owns it until
  * gs_fluid_destroy.  On success *out is the handle; on failure *out is NULL
  * and gs_fluid_last_error(NULL) gives the reason.  Paper: persistent
  * device allocation at initialisation (Section 2.1, AllocateDevice), one
@@ -86,7 +103,8 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz,
 
 /*
  * ComputeTimeStep (Algorithm 1): *dt_out = cfl / max over proper cells of
- * sum_d (|v_d| + c)/h_d for state U (device, [5][nz][ny][nx]).  One
+ * sum_d (|v_d| + c)/h_d for state U (device, layout of the handle's dtype;
+ * the FP32 form reads the head).  FP64 arithmetic in both forms.  One
  * reduction pass over U on the stream, then waits for the stream.  Returns
  * GS_ERR_NONPHYSICAL if U, or any state read since the last waiting call,
  * held a non-physical cell.
@@ -114,6 +132,18 @@ int gs_fluid_step(gs_fluid* h, void* U, double dt);
 int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end,
                      double* dt_log);
 
+/*
+ * Conserved totals: totals[f] = sum over proper cells of field f of U
+ * (host array of 5 doubles), for the FP32 form of head - compensation.  FP64
+ * with error-free (TwoSum) accumulation in a fixed order: deterministic, and
+ * within a few units of the last place of the exact sum.  A diagnostic, not
+ * a step of the paper's algorithm: with periodic boundaries the
+ * finite-volume update conserves these sums up to rounding, since every
+ * face flux enters two cells with opposite signs.  One reduction pass on the
+ * stream, then waits; reports a pending non-physical flag like gs_fluid_sync.
+ */
+int gs_fluid_totals(gs_fluid* h, const void* U, double* totals);
+
 /* Wait for the stream; report a pending non-physical flag. */
 int gs_fluid_sync(gs_fluid* h);
 
@@ -126,7 +156,8 @@ int gs_fluid_set_stream(gs_fluid* h, void* stream);
 
 /*
  * Launch shape of the stage kernels: workgroups of 256 threads own a
- * (256/tile_y) x tile_y column tile (tile_y 8 or 16; 0 = default 16) and
+ * (256/tile_y) x tile_y column tile (tile_y 8 or 16; 0 = the default, 16
+ * for FP64 and 8 for FP32, rows of one 128-byte cache line per field) and
  * march chunk_z planes (>= 1; 0 = chosen from the mesh).  Results do not
  * depend on the shape.
  */

@@ -1,21 +1,28 @@
 """MI355X-native explicit RK2 finite-volume step of the 3D ideal-gas Euler
-equations (FP64), the data-parallel hot path of the Riemann-problem example
-in Budiardja & Cardall, "Targeting GPUs with OpenMP Directives on Summit"
-(arXiv:1812.07977, Section 3, Algorithm 1).
+equations, the data-parallel hot path of the Riemann-problem example in
+Budiardja & Cardall, "Targeting GPUs with OpenMP Directives on Summit"
+(arXiv:1812.07977, Section 3, Algorithm 1), in FP64 or in a compensated FP32
+form.
 
 Python view of libgs_fluid.so: `Fluid` marshals torch tensors (device memory)
 and the current stream into the C ABI; all arithmetic runs in the library's
-HIP kernels.  A state is a float64 CUDA/ROCm tensor of shape (5, nz, ny, nx),
-fields (rho, m_x, m_y, m_z, E), x fastest.
+HIP kernels.  An FP64 state is a float64 GPU tensor of shape (5, nz, ny, nx),
+fields (rho, m_x, m_y, m_z, E), x fastest.  An FP32 state is a float32 GPU
+tensor of shape (2, 5, nz, ny, nx): [0] the head, [1] the Kahan compensation;
+it represents head - compensation.
 """
 import ctypes
 
 from . import _lib
 
-__all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC"]
+__all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC", "F64", "F32"]
 
 OUTFLOW = _lib.GS_BC_OUTFLOW
 PERIODIC = _lib.GS_BC_PERIODIC
+F64 = _lib.GS_F64
+F32 = _lib.GS_F32
+
+_DTYPE_NAMES = {"f64": F64, "f32": F32, F64: F64, F32: F32}
 
 _BC_NAMES = {"outflow": OUTFLOW, "periodic": PERIODIC, OUTFLOW: OUTFLOW, PERIODIC: PERIODIC}
 
@@ -56,40 +63,73 @@ class Fluid:
     gamma   ratio of specific heats (> 1)
     cfl     Courant number in (0, 1]
     bc      "outflow" or "periodic"
+    dtype   "f64" or "f32" (the compensated FP32 form)
     stream  torch stream for all work (default: the current stream)
     """
 
-    def __init__(self, shape, spacing=None, gamma=1.4, cfl=0.5, bc="outflow", stream=None):
+    def __init__(self, shape, spacing=None, gamma=1.4, cfl=0.5, bc="outflow", dtype="f64",
+                 stream=None):
         nx, ny, nz = (int(n) for n in shape)
         if spacing is None:
             h = 1.0 / max(nx, ny, nz)
             spacing = (h, h, h)
         if bc not in _BC_NAMES:
             raise ValueError(f"unknown boundary kind {bc!r}")
+        if dtype not in _DTYPE_NAMES:
+            raise ValueError(f"unknown dtype {dtype!r}")
         self.shape = (nx, ny, nz)
         self.spacing = tuple(float(s) for s in spacing)
         self.gamma = float(gamma)
         self.cfl = float(cfl)
         self.bc = _BC_NAMES[bc]
+        self.dtype = _DTYPE_NAMES[dtype]
         L = _lib.lib()
         handle = ctypes.c_void_p()
         st = _stream_ptr(stream)
         _check(L.gs_fluid_create(nx, ny, nz, *self.spacing, self.gamma, self.cfl, self.bc,
-                                 _lib.GS_F64, st, ctypes.byref(handle)))
+                                 self.dtype, st, ctypes.byref(handle)))
         self._h = handle
         self._stream = st
 
     # -- marshalling ------------------------------------------------------------
+    def state_shape(self):
+        nx, ny, nz = self.shape
+        return (5, nz, ny, nx) if self.dtype == F64 else (2, 5, nz, ny, nx)
+
     def _state_ptr(self, U):
         import torch
-        nx, ny, nz = self.shape
         if not isinstance(U, torch.Tensor):
             raise TypeError("U must be a torch tensor")
-        if U.dtype != torch.float64 or not U.is_cuda:
-            raise TypeError("U must be a float64 tensor on the GPU")
-        if tuple(U.shape) != (5, nz, ny, nx) or not U.is_contiguous():
-            raise ValueError(f"U must be contiguous with shape (5, {nz}, {ny}, {nx})")
+        want = torch.float64 if self.dtype == F64 else torch.float32
+        if U.dtype != want or not U.is_cuda:
+            raise TypeError(f"U must be a {want} tensor on the GPU")
+        if tuple(U.shape) != self.state_shape() or not U.is_contiguous():
+            raise ValueError(f"U must be contiguous with shape {self.state_shape()}")
         return ctypes.c_void_p(U.data_ptr())
+
+    def state_from(self, U):
+        """A device state of this solver's form from FP64 conserved data U
+        (array or tensor of shape (5, nz, ny, nx)).  FP32 form: head = U
+        rounded to FP32, compensation = (head - U) rounded to FP32, so that
+        head - compensation keeps U to about 48 bits."""
+        import torch
+        u = torch.as_tensor(U, dtype=torch.float64)
+        if tuple(u.shape) != self.state_shape()[-4:]:
+            raise ValueError(f"U must have shape {self.state_shape()[-4:]}")
+        u = u.to("cuda")
+        if self.dtype == F64:
+            return u.contiguous()
+        head = u.to(torch.float32)
+        comp = (head.to(torch.float64) - u).to(torch.float32)
+        return torch.stack([head, comp]).contiguous()
+
+    def to_f64(self, S):
+        """FP64 values of a device state of this solver's form (for the FP32
+        form head - compensation, exact in FP64)."""
+        import torch
+        if self.dtype == F64:
+            return S
+        return S[0].to(torch.float64) - S[1].to(torch.float64)
 
     def _handle(self):
         if self._h is None:
@@ -121,6 +161,13 @@ class Fluid:
                 raise ValueError("dt_log must be a contiguous float64 GPU tensor of >= nsteps")
             ptr = ctypes.c_void_p(dt_log.data_ptr())
         _check(_lib.lib().gs_fluid_advance(h, self._state_ptr(U), int(nsteps), float(t_end), ptr), h)
+
+    def totals(self, U):
+        """Conserved totals (5 FP64 sums over cells) of state U; waits."""
+        out = (ctypes.c_double * 5)()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_totals(h, self._state_ptr(U), out), h)
+        return [out[i] for i in range(5)]
 
     def sync(self):
         h = self._handle()
@@ -162,9 +209,9 @@ class Fluid:
         return ms.value, n.value
 
     @staticmethod
-    def workspace_bytes(shape):
+    def workspace_bytes(shape, dtype="f64"):
         nx, ny, nz = shape
-        return _lib.lib().gs_fluid_workspace_bytes(nx, ny, nz, _lib.GS_F64)
+        return _lib.lib().gs_fluid_workspace_bytes(nx, ny, nz, _DTYPE_NAMES[dtype])
 
     def close(self):
         """Wait for queued work, then release the handle."""

@@ -18,6 +18,7 @@ GS_ERR_STATE = -4
 GS_BC_OUTFLOW = 0
 GS_BC_PERIODIC = 1
 GS_F64 = 0
+GS_F32 = 1
 
 # every symbol the header declares: (name, restype, argtypes)
 _VP = ctypes.c_void_p
@@ -32,6 +33,7 @@ SIGNATURES = [
     ("gs_fluid_dt", _I, [_VP, _VP, _PD]),
     ("gs_fluid_step", _I, [_VP, _VP, _D]),
     ("gs_fluid_advance", _I, [_VP, _VP, _I, _D, _VP]),
+    ("gs_fluid_totals", _I, [_VP, _VP, _PD]),
     ("gs_fluid_sync", _I, [_VP]),
     ("gs_fluid_get_time", _I, [_VP, _PD]),
     ("gs_fluid_set_time", _I, [_VP, _D]),

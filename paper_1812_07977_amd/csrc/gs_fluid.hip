@@ -64,6 +64,7 @@ struct DevState {
     unsigned long long rate_dt;  // result slot of the dt reduction
     unsigned int flags;          // bit 0: a non-physical cell was read
     unsigned int pad;
+    double tot[NV];              // conserved totals of the last totals pass
 };
 
 __device__ __forceinline__ int map_index(int i, int n, int periodic)
@@ -98,38 +99,62 @@ __device__ __forceinline__ void block_tile(const Geom& g, int& tx0, int& ty0, in
     kc = chunk;
 }
 
-__device__ __forceinline__ void load5(const double* __restrict__ base, long long field, int off,
-                                      double u[NV])
+template <typename T>
+__device__ __forceinline__ void load5(const T* __restrict__ base, long long field, int off, T u[NV])
 {
 #pragma unroll
     for (int f = 0; f < NV; ++f) u[f] = base[f * field + off];
 }
 
-// Fused RK2 substep.  STAGE 1: Uout = Uin + dU(Uin).  STAGE 2: Uout =
-// 0.5 ((Un + Uin) + dU(Uin)), where Uout may alias Un (each cell's Un is read
-// only by the thread that writes it).  DEVDT: dt = cfl / max rate (slot
-// parity), clipped to t_end; else dt = dt_host.  RATE: accumulate the max
-// signal rate of Uout into rate[parity ^ 1].
+// Fused RK2 substep on states of type T (double: the FP64 form; float: the
+// FP32 form).  STAGE 1: Uout = Uin + dU(Uin); the FP32 form also stores the
+// increment dU(Uin) itself into D0.  STAGE 2, FP64: Uout = 0.5 ((Un + Uin) +
+// dU(Uin)); FP32: the same value written as U(n) plus the increment
+// 0.5 (D0 + dU(Uin)), summed with Kahan compensation, Cn holding the
+// compensation of Un (read and rewritten).  Storing D0 keeps the first
+// substep's increment exact: U(1) - U(n) would have lost whatever part of it
+// falls below the rounding of U(1).  Uout may alias Un (each cell's Un and Cn
+// are read only by the thread that writes them).  DEVDT:
+// dt = cfl / max rate (slot parity), clipped to t_end; else dt = dt_host.
+// RATE: accumulate the max signal rate of Uout into rate[parity ^ 1].
+// Primitive recovery and signal rates run in FP64 for both forms (kd); the
+// reconstruction and flux arithmetic runs in T (kt).
 #ifndef GS_STAGE_WAVES_PER_EU
 #define GS_STAGE_WAVES_PER_EU 2
 #endif
+#ifndef GS_STAGE_WAVES_PER_EU_F32
+#define GS_STAGE_WAVES_PER_EU_F32 3
+#endif
 
-template <int TX, int TY, int STAGE, bool DEVDT, bool RATE>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(GS_STAGE_WAVES_PER_EU)))
-stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geom g, Phys k,
-             DevState* __restrict__ st, int parity, double dt_host, double t_end,
+template <typename T>
+struct StageOcc {
+    static constexpr int waves = sizeof(T) == 8 ? GS_STAGE_WAVES_PER_EU : GS_STAGE_WAVES_PER_EU_F32;
+};
+
+// FP64 constants for the FP64 parts: the FP64 form's own constants, or the
+// separate FP64 set of the FP32 form.
+__device__ __forceinline__ const Phys& phys64(const Phys& kt, const Phys&) { return kt; }
+__device__ __forceinline__ const Phys& phys64(const PhysT<float>&, const Phys& kd) { return kd; }
+
+template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T>::waves)))
+stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom g, PhysT<T> kt,
+             Phys kd, DevState* __restrict__ st, int parity, double dt_host, double t_end,
              double* __restrict__ dt_log, int step)
 {
     constexpr int NT = TX * TY;
     constexpr int WX = TX + 4, WY = TY + 4;
+    constexpr bool KAHAN = (STAGE == 2) && (sizeof(T) == 4);   // FP32 stage 2
+    constexpr bool KEEPD = (STAGE == 1) && (sizeof(T) == 4);   // FP32 stage 1
     static_assert(4 * (TX + TY) <= NT, "one halo cell per thread at most");
     static_assert(TX + TY <= NT, "one edge face per thread at most");
-    __shared__ double Ws[NV][WY][WX];     // primitives of the plane, +2 halo
-    __shared__ double Fx[NV][TY][TX + 1]; // x-face fluxes, face i-1/2 at [i]
-    __shared__ double Fy[NV][TY + 1][TX]; // y-face fluxes, face j-1/2 at [j]
+    __shared__ T Ws[NV][WY][WX];     // primitives of the plane, +2 halo
+    __shared__ T Fx[NV][TY][TX + 1]; // x-face fluxes, face i-1/2 at [i]
+    __shared__ T Fy[NV][TY + 1][TX]; // y-face fluxes, face j-1/2 at [j]
     constexpr int NH = 4 * (TX + TY);     // halo cells of one plane
-    __shared__ double Hr[3][NV][NH];      // halo ring: raw states of 3 planes
+    __shared__ T Hr[3][NV][NH];      // halo ring: raw states of 3 planes
 
+    const Phys& K = phys64(kt, kd);
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
 
@@ -171,13 +196,14 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     // edges of the tile, y-faces above row TY-1 (e < TX) and x-faces right of
     // column TX-1.  Both are evaluated as y-faces: for an x-face the two
     // tangential velocity components are exchanged through the LDS addressing
-    // (and exchanged back on the way out), which yields bit-identical values
-    // since every sum and product involved is commutative.
+    // (and exchanged back on the way out); hll_flux orders its one
+    // cross-component sum so that this performs the very operations of an
+    // x-face evaluation, giving bit-identical fluxes.
     const int e = tid - (NT - (TX + TY));
     constexpr int PLW = WY * WX;               // one field of Ws
     constexpr int PFX = TY * (TX + 1), PFY = (TY + 1) * TX;
     int e_base = 0, e_step = 0, e_v1 = PLW, e_v2 = 2 * PLW;
-    double* e_out = nullptr;
+    T* e_out = nullptr;
     int e_f1 = PFY, e_f2 = 2 * PFY, e_fs = PFY;
     if (e >= 0 && e < TX) {
         e_base = TY * WX + e + 2;
@@ -200,7 +226,7 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     const double t_now = st->t[parity];
     if (DEVDT) {
         double rate = __longlong_as_double((long long)st->rate[parity]);
-        dt = k.cfl / rate;
+        dt = K.cfl / rate;
         if (t_end > 0.0) {
             if (!(t_now < t_end)) dt = 0.0;
             else if (t_now + dt > t_end) dt = t_end - t_now;
@@ -211,9 +237,10 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
         st->rate[parity ^ 1] = 0ull;
         if (dt_log) dt_log[step] = dt;
     }
+    const T dtT = (T)dt;
 
     const long long F = g.field;
-    auto plane_ptr = [&](const double* base, int z) {
+    auto plane_ptr = [&](const T* base, int z) {
         return base + (long long)map_index(z, g.nz, g.periodic) * g.plane;
     };
 
@@ -221,11 +248,11 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
     double rmax = 0.0;
 
     // ---- prologue: planes z0-2 .. z0+2 of the own column, halo of z0 ----
-    double Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
+    T Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
     const int hslot = halo ? tid : 0;
-    double Wk[NV], Wk1[NV], WLz[NV], Fm[NV];
+    T Wk[NV], Wk1[NV], WLz[NV], Fm[NV];
     {
-        double Um2[NV], Um1[NV], Wm2[NV], Wm1[NV];
+        T Um2[NV], Um1[NV], Wm2[NV], Wm1[NV];
         load5(plane_ptr(Uin, z0 - 2), F, own, Um2);
         load5(plane_ptr(Uin, z0 - 1), F, own, Um1);
         load5(plane_ptr(Uin, z0), F, own, Uk);
@@ -235,39 +262,45 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
             // ring: planes z0, z0+1 stored, z0+2 held in registers
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                double h[NV];
+                T h[NV];
                 load5(plane_ptr(Uin, z0 + q), F, hoff, h);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Hr[(z0 + q) % 3][v][hslot] = h[v];
             }
             load5(plane_ptr(Uin, z0 + 2), F, hoff, Hk);
         }
-        bad |= !cons_to_prim(Um2, Wm2, k);
-        bad |= !cons_to_prim(Um1, Wm1, k);
-        bad |= !cons_to_prim(Uk, Wk, k);
-        bad |= !cons_to_prim(Uk1, Wk1, k);
-        face_flux<2>(Wm2, Wm1, Wk, Wk1, k, Fm);  // face z0 - 1/2
+        bad |= !cons_to_prim(Um2, Wm2, K);
+        bad |= !cons_to_prim(Um1, Wm1, K);
+        bad |= !cons_to_prim(Uk, Wk, K);
+        bad |= !cons_to_prim(Uk1, Wk1, K);
+        face_flux<2>(Wm2, Wm1, Wk, Wk1, kt, Fm);  // face z0 - 1/2
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            WLz[v] = __builtin_fma(0.5, minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
+            WLz[v] = fmaR(T(0.5), minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
     }
 
-    double Uon[NV];  // U(n) of the next plane (stage 2), prefetched
+    // U(n) (and, FP32, its compensation and the first increment) of the
+    // next plane in stage 2, prefetched
+    T Uon[NV], Con[NV], Don[NV];
     if (STAGE == 2) load5(Un + (long long)z0 * g.plane, F, own, Uon);
+    if (KAHAN) {
+        load5(Cn + (long long)z0 * g.plane, F, own, Con);
+        load5(D0 + (long long)z0 * g.plane, F, own, Don);
+    }
 
     for (int z = z0; z < z1; ++z) {
         // stage the plane's primitives in LDS
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = Wk[v];
         if (halo) {
-            double w[NV];
-            double h[NV];
+            T w[NV];
+            T h[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 Hr[(z + 2) % 3][v][hslot] = Hk[v];   // plane z+2, loaded last iteration
                 h[v] = Hr[z % 3][v][hslot];           // plane z
             }
-            cons_to_prim(h, w, k);
+            cons_to_prim(h, w, K);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
         }
@@ -275,7 +308,7 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
 
         // in-plane faces: x-face left of the own cell, y-face below it
         {
-            double a[NV], b[NV], c[NV], d[NV], f[NV];
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 a[v] = Ws[v][ty + 2][tx];
@@ -283,7 +316,7 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
                 c[v] = Ws[v][ty + 2][tx + 2];
                 d[v] = Ws[v][ty + 2][tx + 3];
             }
-            face_flux<0>(a, b, c, d, k, f);
+            face_flux<0>(a, b, c, d, kt, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fx[v][ty][tx] = f[v];
 #pragma unroll
@@ -292,24 +325,24 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
                 b[v] = Ws[v][ty + 1][tx + 2];
                 d[v] = Ws[v][ty + 3][tx + 2];
             }
-            face_flux<1>(a, b, c, d, k, f);
+            face_flux<1>(a, b, c, d, kt, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fy[v][ty][tx] = f[v];
         }
         // faces on the far edges of the tile (one evaluation per lane)
         if (e >= 0) {
-            const double* ws = &Ws[0][0][0];
+            const T* ws = &Ws[0][0][0];
             const int off[NV] = {0, e_v1, e_v2, 3 * PLW, 4 * PLW};
-            double a[NV], b[NV], c[NV], d[NV], f[NV];
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double* p = ws + off[v] + e_base;
+                const T* p = ws + off[v] + e_base;
                 a[v] = p[0];
                 b[v] = p[e_step];
                 c[v] = p[2 * e_step];
                 d[v] = p[3 * e_step];
             }
-            face_flux<1>(a, b, c, d, k, f);
+            face_flux<1>(a, b, c, d, kt, f);
             e_out[0] = f[0];
             e_out[e_f1] = f[1];
             e_out[e_f2] = f[2];
@@ -318,9 +351,9 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
         }
         __syncthreads();
 
-        // prefetch plane z+3 of the own column and of the halo, and U(n) of
-        // the next plane (stage 2)
-        double Uk3[NV], Uo[NV];
+        // prefetch plane z+3 of the own column and of the halo, and U(n)
+        // (with its compensation) of the next plane in stage 2
+        T Uk3[NV], Uo[NV], Co[NV], Do[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
         if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
         if (STAGE == 2) {
@@ -328,45 +361,72 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
             for (int v = 0; v < NV; ++v) Uo[v] = Uon[v];
             if (z + 1 < z1) load5(Un + (long long)(z + 1) * g.plane, F, own, Uon);
         }
-
-        // z-face above the own cell, from the register queue
-        double Fp[NV], W2[NV];
-        {
-            double R[NV];
-            bad |= !cons_to_prim(Uk2, W2, k);
+        if (KAHAN) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double w0 = Ws[v][ty + 2][tx + 2];
-                double s1 = minmod(Wk1[v] - w0, W2[v] - Wk1[v]);
-                R[v] = __builtin_fma(-0.5, s1, Wk1[v]);
-                Wk[v] = __builtin_fma(0.5, s1, Wk1[v]);  // left state of face z+3/2
+                Co[v] = Con[v];
+                Do[v] = Don[v];
             }
-            hll_flux<2>(WLz, R, k, Fp);
+            if (z + 1 < z1) {
+                load5(Cn + (long long)(z + 1) * g.plane, F, own, Con);
+                load5(D0 + (long long)(z + 1) * g.plane, F, own, Don);
+            }
+        }
+
+        // z-face above the own cell, from the register queue
+        T Fp[NV], W2[NV];
+        {
+            T R[NV];
+            bad |= !cons_to_prim(Uk2, W2, K);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const T w0 = Ws[v][ty + 2][tx + 2];
+                T s1 = minmod(Wk1[v] - w0, W2[v] - Wk1[v]);
+                R[v] = fmaR(T(-0.5), s1, Wk1[v]);
+                Wk[v] = fmaR(T(0.5), s1, Wk1[v]);  // left state of face z+3/2
+            }
+            hll_flux<2>(WLz, R, kt, Fp);
         }
 
         // divergence, RK combine, store
         {
-            double out[NV];
+            T out[NV], aux[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double acc = (Fx[v][ty][tx + 1] - Fx[v][ty][tx]) * k.inv_h[0];
-                acc = acc + (Fy[v][ty + 1][tx] - Fy[v][ty][tx]) * k.inv_h[1];
-                acc = acc + (Fp[v] - Fm[v]) * k.inv_h[2];
-                double du = -dt * acc;
-                if (STAGE == 1)
+                T acc = (Fx[v][ty][tx + 1] - Fx[v][ty][tx]) * kt.inv_h[0];
+                acc = acc + (Fy[v][ty + 1][tx] - Fy[v][ty][tx]) * kt.inv_h[1];
+                acc = acc + (Fp[v] - Fm[v]) * kt.inv_h[2];
+                T du = -dtT * acc;
+                if (STAGE == 1) {
                     out[v] = Uk[v] + du;
-                else
-                    out[v] = 0.5 * ((Uo[v] + Uk[v]) + du);
+                    aux[v] = du;
+                } else if (!KAHAN) {
+                    out[v] = T(0.5) * ((Uo[v] + Uk[v]) + du);
+                } else {
+                    // U(n+1) = U(n) + inc, inc = 0.5 (dU(U(n)) + dU(U(1))),
+                    // summed with Kahan compensation: the represented value
+                    // is head - compensation
+                    T inc = T(0.5) * (Do[v] + du);
+                    T y = inc - Co[v];
+                    T s = Uo[v] + y;
+                    aux[v] = (s - Uo[v]) - y;
+                    out[v] = s;
+                }
             }
             if (active) {
-                double* po = Uout + (long long)z * g.plane + own;
+                T* po = Uout + (long long)z * g.plane + own;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) po[v * F] = out[v];
+                if (KAHAN || KEEPD) {
+                    T* pa = (KAHAN ? Cn : D0) + (long long)z * g.plane + own;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) pa[v * F] = aux[v];
+                }
             }
             if (RATE && active) {
-                double w[NV];
-                cons_to_prim(out, w, k);
-                rmax = __builtin_fmax(rmax, signal_rate(w, k));
+                double r;
+                cell_rate(out, K, r);
+                rmax = __builtin_fmax(rmax, r);
             }
         }
 
@@ -393,12 +453,13 @@ stage_kernel(const double* __restrict__ Uin, const double* Un, double* Uout, Geo
 }
 
 // Max signal rate over all cells of U (first pass: one partial per block) and
-// the non-physical flag.
+// the non-physical flag.  For the FP32 form U is the head of the state.
 constexpr int RED_THREADS = 256;
 constexpr int RED_BLOCKS = 1024;
 
+template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
-rate_partial_kernel(const double* __restrict__ U, long long ncell, Phys k,
+rate_partial_kernel(const T* __restrict__ U, long long ncell, Phys k,
                     double* __restrict__ partial, DevState* __restrict__ st)
 {
     __shared__ double red[RED_THREADS / 64];
@@ -406,11 +467,12 @@ rate_partial_kernel(const double* __restrict__ U, long long ncell, Phys k,
     bool bad = false;
     for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * RED_THREADS) {
-        double u[NV], w[NV];
+        T u[NV];
 #pragma unroll
         for (int f = 0; f < NV; ++f) u[f] = U[f * ncell + c];
-        bad |= !cons_to_prim(u, w, k);
-        rmax = __builtin_fmax(rmax, signal_rate(w, k));
+        double r;
+        bad |= !cell_rate(u, k, r);
+        rmax = __builtin_fmax(rmax, r);
     }
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->flags, 1u);
     for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
@@ -440,6 +502,80 @@ rate_final_kernel(const double* __restrict__ partial, int n, unsigned long long*
     }
 }
 
+// Conserved totals in FP64: a running (sum, error) pair per field, the error
+// collected by the exact TwoSum transformation (Knuth), so each total is
+// the rounded exact sum up to second-order terms.  The partition of cells
+// over threads and the combining tree are fixed, so the result is
+// deterministic.  For the FP32 form each cell's value is head - compensation,
+// exact in FP64.
+__device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
+{
+    double t = s + x;
+    double bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
+__device__ __forceinline__ void pair_add(double& s, double& c, double s2, double c2)
+{
+    two_sum_add(s, c, s2);
+    c += c2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+totals_partial_kernel(const T* __restrict__ U, const T* __restrict__ C, long long ncell,
+                      double* __restrict__ partial)
+{
+    __shared__ double red[2 * NV][RED_THREADS / 64];
+    double s[NV], c[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) s[f] = c[f] = 0.0;
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ncell;
+         i += (long long)gridDim.x * RED_THREADS) {
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+            double x = (double)U[f * ncell + i];
+            if (C) x -= (double)C[f * ncell + i];
+            two_sum_add(s[f], c[f], x);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        for (int off = 32; off > 0; off >>= 1) {
+            double s2 = __shfl_xor(s[f], off), c2 = __shfl_xor(c[f], off);
+            pair_add(s[f], c[f], s2, c2);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[2 * f][threadIdx.x >> 6] = s[f];
+            red[2 * f + 1][threadIdx.x >> 6] = c[f];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int f = threadIdx.x;
+        double S = red[2 * f][0], Cc = red[2 * f + 1][0];
+        for (int w = 1; w < RED_THREADS / 64; ++w) pair_add(S, Cc, red[2 * f][w], red[2 * f + 1][w]);
+        partial[(long long)blockIdx.x * 2 * NV + 2 * f] = S;
+        partial[(long long)blockIdx.x * 2 * NV + 2 * f + 1] = Cc;
+    }
+}
+
+// Second pass: one wave per field combines the partial pairs of all blocks
+// in a fixed order and stores sum + error into tot[f].
+__global__ void __launch_bounds__(64 * NV)
+totals_final_kernel(const double* __restrict__ partial, int n, DevState* __restrict__ st)
+{
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0, c = 0.0;
+    for (int b = lane; b < n; b += 64) pair_add(s, c, partial[2 * NV * b + 2 * f], partial[2 * NV * b + 2 * f + 1]);
+    for (int off = 32; off > 0; off >>= 1) {
+        double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+        pair_add(s, c, s2, c2);
+    }
+    if (lane == 0) st->tot[f] = s + c;
+}
+
 // Small state writes, as kernels so that the host never records a memset.
 __global__ void init_state_kernel(DevState* st)
 {
@@ -448,6 +584,7 @@ __global__ void init_state_kernel(DevState* st)
     st->rate_dt = 0ull;
     st->flags = 0u;
     st->pad = 0u;
+    for (int f = 0; f < NV; ++f) st->tot[f] = 0.0;
 }
 
 __global__ void set_time_kernel(DevState* st, int parity, double t) { st->t[parity] = t; }
@@ -475,10 +612,12 @@ struct gs_fluid {
     double h[3];
     double gamma, cfl;
     int bc;
+    int dtype;             // GS_F64 or GS_F32
+    size_t esize;          // bytes per state element
     int device;
     hipStream_t stream;
-    double* U1;            // first-substep result (workspace)
-    double* partial;       // dt-reduction partials
+    void* U1;              // first-substep result (workspace)
+    double* partial;       // reduction partials
     DevState* st;          // device words
     DevState* host_st;     // pinned host mirror for waiting calls
     int parity;
@@ -518,6 +657,26 @@ Phys make_phys(const gs_fluid* h)
     return k;
 }
 
+// The FP64 constants rounded to FP32 for the FP32 form's flux arithmetic.
+PhysT<float> make_phys32(const gs_fluid* h)
+{
+    const Phys d = make_phys(h);
+    PhysT<float> k;
+    k.gamma = (float)d.gamma;
+    k.gm1 = (float)d.gm1;
+    k.inv_gm1 = (float)d.inv_gm1;
+    for (int a = 0; a < 3; ++a) k.inv_h[a] = (float)d.inv_h[a];
+    k.cfl = (float)d.cfl;
+    return k;
+}
+
+template <typename T>
+PhysT<T> phys_t(const gs_fluid* h);
+template <>
+PhysT<double> phys_t<double>(const gs_fluid* h) { return make_phys(h); }
+template <>
+PhysT<float> phys_t<float>(const gs_fluid* h) { return make_phys32(h); }
+
 struct Launch {
     Geom g;
     int tx, ty;
@@ -527,7 +686,9 @@ struct Launch {
 Launch make_launch(const gs_fluid* h)
 {
     Launch L;
-    L.ty = (h->tile_y == 0) ? 16 : h->tile_y;
+    // default tile rows span one 128-byte cache line per field: 16 doubles
+    // or 32 floats
+    L.ty = (h->tile_y != 0) ? h->tile_y : (h->dtype == GS_F32 ? 8 : 16);
     L.tx = 256 / L.ty;
     Geom& g = L.g;
     g.nx = h->nx;
@@ -588,16 +749,20 @@ void prof_end(gs_fluid* h, int kernel, hipEvent_t start)
     h->ev_used[kernel].push_back({start, e});
 }
 
-template <int TX, int TY>
+// One substep launch.  FP32 form: C is the compensation of Un (stage 2) and
+// D the first substep's increment (written by stage 1, read by stage 2);
+// FP64 form: both null.
+template <typename T, int TX, int TY>
 hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, bool rate,
-                          const double* Uin, const double* Un, double* Uout, double dt_host,
+                          const T* Uin, const T* Un, T* Uout, T* C, T* D, double dt_host,
                           double t_end, double* dt_log, int step)
 {
-    const Phys k = make_phys(h);
+    const PhysT<T> kt = phys_t<T>(h);
+    const Phys kd = make_phys(h);
     dim3 grid(L.blocks), block(TX * TY);
-#define GS_LAUNCH(S, D, R)                                                                      \
-    hipLaunchKernelGGL((stage_kernel<TX, TY, S, D, R>), grid, block, 0, h->stream, Uin, Un, Uout, \
-                       L.g, k, h->st, h->parity, dt_host, t_end, dt_log, step)
+#define GS_LAUNCH(S_, D_, R_)                                                                    \
+    hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_>), grid, block, 0, h->stream, Uin, Un, \
+                       Uout, C, D, L.g, kt, kd, h->st, h->parity, dt_host, t_end, dt_log, step)
     if (stage == 1) {
         if (devdt) GS_LAUNCH(1, true, false);
         else GS_LAUNCH(1, false, false);
@@ -614,32 +779,62 @@ hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, b
     return hipGetLastError();
 }
 
-hipError_t launch_stage(gs_fluid* h, int stage, bool devdt, bool rate, const double* Uin,
-                        const double* Un, double* Uout, double dt_host, double t_end,
-                        double* dt_log, int step)
+template <typename T>
+hipError_t launch_stage(gs_fluid* h, int stage, bool devdt, bool rate, const T* Uin, const T* Un,
+                        T* Uout, T* C, T* D, double dt_host, double t_end, double* dt_log,
+                        int step)
 {
     Launch L = make_launch(h);
     hipEvent_t ev = prof_begin(h);
     hipError_t e;
     if (L.ty == 8)
-        e = launch_stage_t<32, 8>(h, L, stage, devdt, rate, Uin, Un, Uout, dt_host, t_end, dt_log, step);
+        e = launch_stage_t<T, 32, 8>(h, L, stage, devdt, rate, Uin, Un, Uout, C, D, dt_host,
+                                     t_end, dt_log, step);
     else
-        e = launch_stage_t<16, 16>(h, L, stage, devdt, rate, Uin, Un, Uout, dt_host, t_end, dt_log, step);
+        e = launch_stage_t<T, 16, 16>(h, L, stage, devdt, rate, Uin, Un, Uout, C, D, dt_host,
+                                      t_end, dt_log, step);
     prof_end(h, stage == 1 ? K_STAGE1 : K_STAGE2, ev);
     return e;
 }
 
-hipError_t launch_rate(gs_fluid* h, const double* U, unsigned long long* dst)
+int reduction_blocks(const gs_fluid* h)
 {
     const long long ncell = (long long)h->nx * h->ny * h->nz;
     long long want = (ncell + RED_THREADS - 1) / RED_THREADS;
-    int blocks = (int)(want < RED_BLOCKS ? want : RED_BLOCKS);
+    return (int)(want < RED_BLOCKS ? want : RED_BLOCKS);
+}
+
+hipError_t launch_rate(gs_fluid* h, const void* U, unsigned long long* dst)
+{
+    const long long ncell = (long long)h->nx * h->ny * h->nz;
+    const int blocks = reduction_blocks(h);
     hipEvent_t ev = prof_begin(h);
-    hipLaunchKernelGGL(rate_partial_kernel, dim3(blocks), dim3(RED_THREADS), 0, h->stream, U, ncell,
-                       make_phys(h), h->partial, h->st);
+    if (h->dtype == GS_F32)
+        hipLaunchKernelGGL(rate_partial_kernel<float>, dim3(blocks), dim3(RED_THREADS), 0,
+                           h->stream, (const float*)U, ncell, make_phys(h), h->partial, h->st);
+    else
+        hipLaunchKernelGGL(rate_partial_kernel<double>, dim3(blocks), dim3(RED_THREADS), 0,
+                           h->stream, (const double*)U, ncell, make_phys(h), h->partial, h->st);
     hipLaunchKernelGGL(rate_final_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream, h->partial,
                        blocks, dst);
     prof_end(h, K_RATE, ev);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(gs_fluid* h, const void* U)
+{
+    const long long ncell = (long long)h->nx * h->ny * h->nz;
+    const int blocks = reduction_blocks(h);
+    if (h->dtype == GS_F32) {
+        const float* u = (const float*)U;
+        hipLaunchKernelGGL(totals_partial_kernel<float>, dim3(blocks), dim3(RED_THREADS), 0,
+                           h->stream, u, u + NV * ncell, ncell, h->partial);
+    } else {
+        hipLaunchKernelGGL(totals_partial_kernel<double>, dim3(blocks), dim3(RED_THREADS), 0,
+                           h->stream, (const double*)U, (const double*)nullptr, ncell, h->partial);
+    }
+    hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(64 * NV), 0, h->stream, h->partial,
+                       blocks, h->st);
     return hipGetLastError();
 }
 
@@ -660,7 +855,8 @@ int sync_state(gs_fluid* h)
     return GS_OK;
 }
 
-bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+bool aligned8(const void* p) { return aligned_to(p, 8); }
 
 // Device address of a word of the handle's DevState.
 unsigned long long* rate_slot(gs_fluid* h, int which)
@@ -670,15 +866,76 @@ unsigned long long* rate_slot(gs_fluid* h, int which)
     return (unsigned long long*)(base + offsetof(DevState, rate) + which * sizeof(unsigned long long));
 }
 
+size_t elem_size(int dtype) { return dtype == GS_F32 ? sizeof(float) : sizeof(double); }
+
+// Substep workspace: U(1); the FP32 form also keeps the first increment.
+long long state_work_bytes(long long ncell, int dtype)
+{
+    return ncell * NV * (long long)elem_size(dtype) * (dtype == GS_F32 ? 2 : 1);
+}
+
+// Checks the state pointer of a call: present and aligned to the element.
+int check_state(gs_fluid* h, const void* U)
+{
+    if (!U || !aligned_to(U, h->esize))
+        return fail(h, GS_ERR_ARG, "U is NULL or not aligned to its element size");
+    return GS_OK;
+}
+
+// Work arrays of one step: the compensation half of the caller's FP32 state,
+// and the first substep's increment (second half of the FP32 workspace).
+template <typename T>
+struct StepArrays {
+    T* u1;
+    T* comp;
+    T* d0;
+};
+
+template <typename T>
+StepArrays<T> step_arrays(gs_fluid* h, T* u)
+{
+    const long long ncell = (long long)h->nx * h->ny * h->nz;
+    StepArrays<T> a;
+    a.u1 = (T*)h->U1;
+    a.comp = (sizeof(T) == 4) ? u + NV * ncell : nullptr;
+    a.d0 = (sizeof(T) == 4) ? a.u1 + NV * ncell : nullptr;
+    return a;
+}
+
+template <typename T>
+hipError_t step_t(gs_fluid* h, T* u, double dt)
+{
+    StepArrays<T> a = step_arrays(h, u);
+    hipError_t e = launch_stage<T>(h, 1, false, false, u, u, a.u1, nullptr, a.d0, dt, 0.0,
+                                   nullptr, 0);
+    if (e == hipSuccess)
+        e = launch_stage<T>(h, 2, false, false, a.u1, u, u, a.comp, a.d0, dt, 0.0, nullptr, 0);
+    return e;
+}
+
+template <typename T>
+hipError_t advance_t(gs_fluid* h, T* u, int nsteps, double t_end, double* dt_log)
+{
+    StepArrays<T> a = step_arrays(h, u);
+    hipError_t e = launch_rate(h, u, rate_slot(h, h->parity));
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+        e = launch_stage<T>(h, 1, true, false, u, u, a.u1, nullptr, a.d0, 0.0, t_end, dt_log, s);
+        if (e == hipSuccess)
+            e = launch_stage<T>(h, 2, true, true, a.u1, u, u, a.comp, a.d0, 0.0, t_end, dt_log, s);
+        h->parity ^= 1;
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
 
 long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || dtype != GS_F64) return -1;
+    if (nx < 1 || ny < 1 || nz < 1 || (dtype != GS_F64 && dtype != GS_F32)) return -1;
     long long ncell = (long long)nx * ny * nz;
-    return ncell * NV * (long long)sizeof(double) + RED_BLOCKS * (long long)sizeof(double) +
+    return state_work_bytes(ncell, dtype) + RED_BLOCKS * 2 * NV * (long long)sizeof(double) +
            (long long)sizeof(DevState);
 }
 
@@ -700,7 +957,8 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
         return fail(nullptr, GS_ERR_ARG, "cfl must be in (0, 1]");
     if (bc != GS_BC_OUTFLOW && bc != GS_BC_PERIODIC)
         return fail(nullptr, GS_ERR_ARG, "unknown boundary kind");
-    if (dtype != GS_F64) return fail(nullptr, GS_ERR_ARG, "unsupported dtype (only GS_F64)");
+    if (dtype != GS_F64 && dtype != GS_F32)
+        return fail(nullptr, GS_ERR_ARG, "unknown dtype (GS_F64 or GS_F32)");
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -722,6 +980,8 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
     h->gamma = gamma;
     h->cfl = cfl;
     h->bc = bc;
+    h->dtype = dtype;
+    h->esize = elem_size(dtype);
     h->device = dev;
     h->stream = (hipStream_t)stream;
     h->U1 = nullptr;
@@ -733,9 +993,9 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
     h->chunk_z = 0;
     h->profile = false;
 
-    const size_t state_bytes = (size_t)nx * ny * nz * NV * sizeof(double);
-    if ((e = hipMalloc((void**)&h->U1, state_bytes)) != hipSuccess ||
-        (e = hipMalloc((void**)&h->partial, RED_BLOCKS * sizeof(double))) != hipSuccess ||
+    const size_t state_bytes = (size_t)state_work_bytes((long long)nx * ny * nz, dtype);
+    if ((e = hipMalloc(&h->U1, state_bytes)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->partial, RED_BLOCKS * 2 * NV * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&h->st, sizeof(DevState))) != hipSuccess ||
         (e = hipHostMalloc((void**)&h->host_st, sizeof(DevState), hipHostMallocDefault)) !=
             hipSuccess) {
@@ -756,9 +1016,9 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
 int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out)
 {
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
-    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
     if (!dt_out) return fail(h, GS_ERR_ARG, "dt_out is NULL");
-    hipError_t e = launch_rate(h, (const double*)U, rate_slot(h, -1));
+    hipError_t e = launch_rate(h, U, rate_slot(h, -1));
     if (e != hipSuccess) return hip_fail(h, e, "dt reduction launch");
     int r = sync_state(h);
     if (r != GS_OK) return r;
@@ -772,11 +1032,9 @@ int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out)
 int gs_fluid_step(gs_fluid* h, void* U, double dt)
 {
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
-    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
     if (!finite_pos(dt)) return fail(h, GS_ERR_ARG, "dt must be finite and > 0");
-    double* u = (double*)U;
-    hipError_t e = launch_stage(h, 1, false, false, u, u, h->U1, dt, 0.0, nullptr, 0);
-    if (e == hipSuccess) e = launch_stage(h, 2, false, false, h->U1, u, u, dt, 0.0, nullptr, 0);
+    hipError_t e = (h->dtype == GS_F32) ? step_t(h, (float*)U, dt) : step_t(h, (double*)U, dt);
     if (e != hipSuccess) return hip_fail(h, e, "stage launch");
     h->parity ^= 1;
     return GS_OK;
@@ -785,20 +1043,27 @@ int gs_fluid_step(gs_fluid* h, void* U, double dt)
 int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end, double* dt_log)
 {
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
-    if (!U || !aligned8(U)) return fail(h, GS_ERR_ARG, "U is NULL or not 8-byte aligned");
+    if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
     if (nsteps < 0) return fail(h, GS_ERR_ARG, "nsteps must be >= 0");
     if (!std::isfinite(t_end) || t_end < 0.0) return fail(h, GS_ERR_ARG, "t_end must be finite and >= 0");
     if (dt_log && !aligned8(dt_log)) return fail(h, GS_ERR_ARG, "dt_log not 8-byte aligned");
     if (nsteps == 0) return GS_OK;
-    double* u = (double*)U;
-    hipError_t e = launch_rate(h, u, rate_slot(h, h->parity));
-    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
-        e = launch_stage(h, 1, true, false, u, u, h->U1, 0.0, t_end, dt_log, s);
-        if (e == hipSuccess) e = launch_stage(h, 2, true, true, h->U1, u, u, 0.0, t_end, dt_log, s);
-        h->parity ^= 1;
-    }
+    hipError_t e = (h->dtype == GS_F32) ? advance_t(h, (float*)U, nsteps, t_end, dt_log)
+                                        : advance_t(h, (double*)U, nsteps, t_end, dt_log);
     if (e != hipSuccess) return hip_fail(h, e, "advance launch");
     return GS_OK;
+}
+
+int gs_fluid_totals(gs_fluid* h, const void* U, double* totals)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
+    if (!totals) return fail(h, GS_ERR_ARG, "totals is NULL");
+    hipError_t e = launch_totals(h, U);
+    if (e != hipSuccess) return hip_fail(h, e, "totals launch");
+    int r = sync_state(h);
+    for (int f = 0; f < NV; ++f) totals[f] = h->host_st->tot[f];
+    return r;
 }
 
 int gs_fluid_sync(gs_fluid* h)

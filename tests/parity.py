@@ -78,3 +78,52 @@ def gpu_run_device_dt(U0, bc, nsteps, t_end=0.0, launch=None):
         out = to_cpu(U)
         dts = log.cpu().numpy()[:nsteps]
     return out, dts, t
+
+
+# ---------------------------------------------------------------------------
+# the FP32 form: states are (head, compensation) pairs; results are compared
+# as head - compensation in FP64
+# ---------------------------------------------------------------------------
+
+def f32_run(U0, bc, nsteps, mode="device", dts=None, launch=None, t_end=0.0):
+    """Runs the FP32 form from FP64 initial data U0.  mode "device":
+    gs_fluid_advance; "host": gs_fluid_dt + gs_fluid_step per step; "given":
+    gs_fluid_step with the dt sequence dts.  Returns (U as FP64 numpy,
+    dts, final device time, (head, compensation) as numpy float32)."""
+    import torch
+    from paper_1812_07977_amd import Fluid
+    nz, ny, nx = U0.shape[1:]
+    with Fluid((nx, ny, nz), gamma=GAMMA, cfl=CFL, bc=bc, dtype="f32") as F:
+        if launch:
+            F.set_launch(*launch)
+        S = F.state_from(U0)
+        if mode == "device":
+            log = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+            F.advance(S, nsteps, t_end, log)
+            out_dts = log.cpu().numpy()[:nsteps]
+        elif mode == "host":
+            out_dts = []
+            for _ in range(nsteps):
+                dt = F.dt(S)
+                out_dts.append(dt)
+                F.step(S, dt)
+            out_dts = np.array(out_dts)
+        else:
+            for dt in dts:
+                F.step(S, float(dt))
+            out_dts = np.asarray(dts)
+        t = F.time
+        out = to_cpu(F.to_f64(S))
+        pair = to_cpu(S)
+    return out, out_dts, t, pair
+
+
+def rel_l1(gpu, ref):
+    """Per-field sum |gpu - ref| / sum |ref| (a zero field scaled by the
+    largest field sum)."""
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    sums = [float(np.sum(np.abs(ref[f]))) for f in range(ref.shape[0])]
+    big = max(sums)
+    return [float(np.sum(np.abs(gpu[f] - ref[f])) / (sums[f] if sums[f] > 0 else big))
+            for f in range(ref.shape[0])]

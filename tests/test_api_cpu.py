@@ -55,7 +55,7 @@ def _create(**over):
     dict(dx=0.0), dict(dy=-0.1), dict(dz=math.inf), dict(dx=math.nan),
     dict(gamma=1.0), dict(gamma=0.5), dict(gamma=math.nan),
     dict(cfl=0.0), dict(cfl=1.5), dict(cfl=math.nan),
-    dict(bc=2), dict(bc=-1), dict(dtype=1),
+    dict(bc=2), dict(bc=-1), dict(dtype=2), dict(dtype=-1),
     dict(nx=1 << 16, ny=1 << 16, nz=2),
 ])
 def test_create_rejects_bad_arguments(over):
@@ -78,6 +78,8 @@ def test_null_handle_calls_are_argument_errors():
     assert L.gs_fluid_dt(None, None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_step(None, None, 0.1) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_advance(None, None, 1, 0.0, None) == lib_mod.GS_ERR_ARG
+    tot = (ctypes.c_double * 5)()
+    assert L.gs_fluid_totals(None, None, tot) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_sync(None) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_get_time(None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_set_time(None, 0.0) == lib_mod.GS_ERR_ARG
@@ -89,21 +91,23 @@ def test_null_handle_calls_are_argument_errors():
     assert L.gs_fluid_last_error(None) is not None
 
 
-def test_workspace_bytes():
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_workspace_bytes(dtype):
     L = _lib()
     n = 10 * 20 * 30
-    ws = L.gs_fluid_workspace_bytes(10, 20, 30, 0)
-    assert ws >= n * 5 * 8            # one state array
-    assert ws - n * 5 * 8 < 64 * 1024  # plus a few kilobytes
-    assert L.gs_fluid_workspace_bytes(0, 1, 1, 0) == -1
+    ws = L.gs_fluid_workspace_bytes(10, 20, 30, dtype)
+    assert ws >= n * 5 * 8                  # U(1), and for FP32 its increment
+    assert ws - n * 5 * 8 < 128 * 1024      # plus reduction partials
+    assert L.gs_fluid_workspace_bytes(0, 1, 1, dtype) == -1
     assert L.gs_fluid_workspace_bytes(1, 1, 1, 7) == -1
 
 
-def test_valid_create_without_gpu_is_a_hip_error():
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_valid_create_without_gpu_is_a_hip_error(dtype):
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    st, h = _create()
+    st, h = _create(dtype=dtype)
     assert st == lib_mod.GS_ERR_HIP
     assert not h.value
 

@@ -132,10 +132,13 @@ def random_plane_params(seed):
     return nrm, d, r_rho, r_p
 
 
-def random_plane(nx, ny, nz, seed, gamma=GAMMA):
+def random_plane(nx, ny, nz, seed, gamma=GAMMA, v=(0.0, 0.0, 0.0)):
     """Seeded Riemann problem: (rho, p) = (1, 1) where n.x < d, and
-    (1/r_rho, 1/r_p) on the other side; v = 0."""
+    (1/r_rho, 1/r_p) on the other side; uniform velocity v (default 0; a
+    non-zero v is the same problem seen from a moving frame)."""
     nrm, d, r_rho, r_p = random_plane_params(seed)
     x, y, z = centres(nx, ny, nz)
     mask = np.broadcast_to(nrm[0] * x + nrm[1] * y + nrm[2] * z < d, (nz, ny, nx))
-    return _two_state(mask, (1.0, 1.0), (1.0 / r_rho, 1.0 / r_p), gamma)
+    rho = np.where(mask, 1.0, 1.0 / r_rho)
+    p = np.where(mask, 1.0, 1.0 / r_p)
+    return conserved(rho, *v, p, (nz, ny, nx), gamma)
