@@ -1,4 +1,5 @@
-"""ctypes declarations of libgs_fluid.so (the C ABI in include/gs_fluid.h).
+"""ctypes declarations of libgs_fluid.so (the C ABI in include/gs_fluid.h and
+include/gs_cnn.h).
 
 Argument marshalling only: every computation runs in the library's kernels.
 Loading fails loudly if the library has not been built; there is no fallback.
@@ -44,6 +45,22 @@ SIGNATURES = [
     ("gs_fluid_workspace_bytes", _LL, [_I, _I, _I, _I]),
     ("gs_fluid_destroy", None, [_VP]),
     ("gs_fluid_last_error", ctypes.c_char_p, [_VP]),
+    # learned-correction network (include/gs_cnn.h)
+    ("gs_cnn_param_count", _I, []),
+    ("gs_cnn_create", _I, [_I, _I, _I, _I, _D, _VP, ctypes.POINTER(_VP)]),
+    ("gs_cnn_set_params", _I, [_VP, _VP]),
+    ("gs_cnn_get_params", _I, [_VP, _VP]),
+    ("gs_cnn_set_norm", _I, [_VP, _PD, _PD, _PD]),
+    ("gs_cnn_forward", _I, [_VP, _VP, _VP]),
+    ("gs_cnn_restrict", _I, [_VP, _VP, _VP]),
+    ("gs_cnn_make_target", _I, [_VP, _VP, _VP, _VP]),
+    ("gs_cnn_gradients", _I, [_VP, _VP, _VP, _VP, _PD]),
+    ("gs_cnn_train_step", _I, [_VP, _VP, _VP, ctypes.c_float, _PD]),
+    ("gs_cnn_correct", _I, [_VP, _VP]),
+    ("gs_cnn_counts", _I, [_VP, _PI, _PI]),
+    ("gs_cnn_set_stream", _I, [_VP, _VP]),
+    ("gs_cnn_destroy", None, [_VP]),
+    ("gs_cnn_last_error", ctypes.c_char_p, [_VP]),
 ]
 
 _lib = None

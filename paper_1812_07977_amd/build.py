@@ -2,7 +2,8 @@
 
     python -m paper_1812_07977_amd.build
 
-Compiles csrc/gs_fluid.hip with hipcc for gfx950 only.  Floating-point
+Compiles csrc/gs_fluid.hip (the Euler step) and csrc/gs_cnn.hip (the
+learned-correction network) with hipcc for gfx950 only, into one library.  Floating-point
 contraction is off (the kernels write every fused multiply-add explicitly)
 and packed FP32 instructions are disabled.
 """
@@ -12,7 +13,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "gs_fluid.hip")
+SRCS = [os.path.join(HERE, "csrc", "gs_fluid.hip"), os.path.join(HERE, "csrc", "gs_cnn.hip")]
 LIB = os.path.join(HERE, "libgs_fluid.so")
 ARCH = "gfx950"
 
@@ -27,7 +28,7 @@ FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), SRC, "-o", LIB + ".tmp"]
+           "-I", os.path.join(HERE, "csrc"), *SRCS, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

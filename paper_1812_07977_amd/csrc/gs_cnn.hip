@@ -1,0 +1,1084 @@
+// gs_cnn.hip -- gfx950 kernels and C ABI of the learned-correction form: a
+// 5 -> 32 -> 32 -> 5 network of 3x3x3 convolutions on BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), its training, and the
+// correction of an FP32 coarse state with a device-side fallback.
+//
+// Layouts.
+//   * CL (channels-last) BF16 activations: act[v * C + c], v = (z ny + y) nx
+//     + x, C = 8 (the 5 input fields padded with zeros) or 32.  One MFMA
+//     operand fragment of 8 channels of one cell is one 16-byte load.
+//   * VM (voxel-major) BF16 copies for the weight gradient: vm[c][v], and
+//     for a layer input three copies shifted by dx = -1, 0, +1 along x (the
+//     boundary map applied while copying), so that every operand fragment of
+//     8 consecutive cells along x is again one aligned 16-byte load.
+//   * Weights in fragment order: for K-block kb and N-block nb, lane l holds
+//     the 8 values of the 16x16x32 B operand it feeds: 64 lanes x 16 bytes.
+//
+// Matrix-core lane layout of v_mfma_f32_16x16x32_bf16 (checked on the
+// device): lane l holds A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j]
+// [l % 16], j = 0..7, and receives D[4 (l / 16) + i][l % 16], i = 0..3.
+//
+// Forward convolution as an implicit GEMM: M = cells (16 consecutive x of a
+// row per M-block), N = output channels, K = 27 taps x input channels (one
+// tap of 32 channels, or four taps of 8, per 32-wide K-block).  The input
+// gradient of a convolution on a periodic mesh is the convolution of the
+// output gradient with mirrored taps and transposed channels, so the same
+// kernel runs the backward pass, with the ReLU mask fused into its epilogue.
+// The weight gradient is a GEMM over cells (K = cells): M = input channels,
+// N = output channels, per tap; partial sums per wave, reduced in a fixed
+// order by a second kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "euler_math.hpp"
+#include "gs_cnn.h"
+#include "gs_fluid.h"
+
+namespace gsc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int NF = 5;       // conserved fields
+constexpr int HID = 32;     // hidden channels
+constexpr int TAPS = 27;
+constexpr int THREADS = 256;
+
+// parameter layout (floats)
+constexpr int W1_N = HID * NF * TAPS, B1_N = HID;
+constexpr int W2_N = HID * HID * TAPS, B2_N = HID;
+constexpr int W3_N = NF * HID * TAPS, B3_N = NF;
+constexpr int W1_OFF = 0, B1_OFF = W1_OFF + W1_N;
+constexpr int W2_OFF = B1_OFF + B1_N, B2_OFF = W2_OFF + W2_N;
+constexpr int W3_OFF = B2_OFF + B2_N, B3_OFF = W3_OFF + W3_N;
+constexpr int P_N = B3_OFF + B3_N;
+
+// BF16 <-> FP32, round to nearest even (inputs are finite)
+__device__ __forceinline__ u16 f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ int wrap_or_clamp(int i, int n, int periodic)
+{
+    if (periodic) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// weight packing
+// ---------------------------------------------------------------------------
+
+// Fragment-ordered BF16 weights of one convolution from the FP32 master
+// array W[cout][cin][27].  CINP = 32: K-block kb = tap kb, k = input
+// channel; CINP = 8: K-block kb = taps 4kb .. 4kb+3 (lane group), k = input
+// channel (< 8).  MIRROR: the backward (input-gradient) convolution, whose
+// input channels are the forward's outputs, output channels the forward's
+// inputs, and tap t the forward's tap 26 - t.  Entries outside the logical
+// sizes are zero.
+__global__ void pack_weights_kernel(const float* __restrict__ W, int cin, int cout, int cinp,
+                                    int nb_count, int kb_count, int mirror, u16* __restrict__ out)
+{
+    const int total = kb_count * nb_count * 64 * 8;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int j = e & 7, l = (e >> 3) & 63, frag = e >> 9;
+        const int nb = frag % nb_count, kb = frag / nb_count;
+        int tap, ci;
+        if (cinp == 32) {
+            tap = kb;
+            ci = 8 * (l >> 4) + j;
+        } else {
+            tap = 4 * kb + (l >> 4);
+            ci = j;
+        }
+        const int co = 16 * nb + (l & 15);
+        float w = 0.0f;
+        if (tap < TAPS) {
+            // forward view: out channel co, in channel ci, tap
+            // mirror view: out channel co = forward input, in channel ci =
+            // forward output, tap mirrored
+            const int fo = mirror ? ci : co, fi = mirror ? co : ci;
+            const int ft = mirror ? TAPS - 1 - tap : tap;
+            if (fo < cout && fi < cin) w = W[(fo * cin + fi) * TAPS + ft];
+        }
+        out[e] = f2bf(w);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// convolution (forward, and input gradient with mirrored weights)
+// ---------------------------------------------------------------------------
+
+enum { EPI_RELU_BF16 = 0, EPI_F32_SOA = 1, EPI_MASK_BF16 = 2 };
+
+struct ConvGeom {
+    int nx, ny, nz;
+    int periodic;
+    int ntx, nty;   // 16 x 16 tiles
+    int kz;         // planes per workgroup
+};
+
+// X: CL input with CINP channels.  Wp: fragment-packed weights.  Output per
+// EPI: RELU_BF16 -> CL BF16 [v][16 NB] of max(acc + bias, 0); F32_SOA ->
+// FP32 [co][v] for co < cout_valid, acc + bias; MASK_BF16 -> CL BF16 of acc
+// where mask (CL BF16, same shape) is positive, else 0.
+template <int CINP, int NB, int EPI>
+__global__ void __launch_bounds__(THREADS)
+conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* __restrict__ bias,
+            void* __restrict__ out, const u16* __restrict__ mask, ConvGeom g, int cout_valid)
+{
+    constexpr int KB = (CINP == 32) ? TAPS : 7;
+    constexpr int COUT = 16 * NB;
+    __shared__ u32x4 Wl[KB * NB * 64];
+    for (int i = threadIdx.x; i < KB * NB * 64; i += THREADS) Wl[i] = ((const u32x4*)Wp)[i];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int xl = l & 15, grp = l >> 4;
+    const int ntile = g.ntx * g.nty;
+    const int tile = blockIdx.x % ntile, chunk = blockIdx.x / ntile;
+    const int x0 = (tile % g.ntx) * 16, y0 = (tile / g.ntx) * 16;
+    const int z0 = chunk * g.kz, z1 = min(z0 + g.kz, g.nz);
+    const long long ncell = (long long)g.nx * g.ny * g.nz;
+    const int xa = x0 + xl;  // the cell whose A row this lane loads
+
+    for (int z = z0; z < z1; ++z) {
+        f32x4 acc[4][NB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 3
+        for (int kb = 0; kb < KB; ++kb) {
+            int tap = (CINP == 32) ? kb : 4 * kb + grp;
+            if (tap >= TAPS) tap = 13;  // padding taps carry zero weights
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int zs = wrap_or_clamp(z + dz, g.nz, g.periodic);
+            const int xs = wrap_or_clamp(xa + dx, g.nx, g.periodic);
+            u32x4 a[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ys = wrap_or_clamp(y0 + 4 * wave + r + dy, g.ny, g.periodic);
+                const long long v = ((long long)zs * g.ny + ys) * g.nx + xs;
+                const long long off = (CINP == 32) ? v * 32 + 8 * grp : v * 8;
+                a[r] = *(const u32x4*)(X + off);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const u32x4 b = Wl[(kb * NB + nb) * 64 + l];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][nb] = mfma(a[r], b, acc[r][nb]);
+            }
+        }
+
+        // epilogue: lane holds D[4 grp + i][xl]: cell x0 + 4 grp + i, channel
+        // 16 nb + xl
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = y0 + 4 * wave + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * grp + i;
+                if (x >= g.nx || y >= g.ny) continue;
+                const long long v = ((long long)z * g.ny + y) * g.nx + x;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int co = 16 * nb + xl;
+                    const float s = acc[r][nb][i];
+                    if (EPI == EPI_RELU_BF16) {
+                        ((u16*)out)[v * COUT + co] = f2bf(fmaxf(s + bias[co], 0.0f));
+                    } else if (EPI == EPI_F32_SOA) {
+                        if (co < cout_valid) ((float*)out)[co * ncell + v] = s + bias[co];
+                    } else {
+                        const bool on = (mask[v * COUT + co] & 0x7FFFu) != 0;
+                        ((u16*)out)[v * COUT + co] = on ? f2bf(s) : (u16)0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient
+// ---------------------------------------------------------------------------
+
+// CL [v][C] -> VM copies out[s][c][v], c < C16 (channels >= C are zero),
+// copy s shifted by s - (ns == 3 ? 1 : 0) along x.
+__global__ void to_vm_kernel(const u16* __restrict__ in, int C, int C16, int ns, int nx, int ny,
+                             int nz, int periodic, u16* __restrict__ out)
+{
+    const long long ncell = (long long)nx * ny * nz;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell * ns;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(e / ncell);
+        const long long v = e - s * ncell;
+        const int x = (int)(v % nx);
+        const long long row = v - x;
+        const int dx = s - (ns == 3 ? 1 : 0);
+        const long long src = row + wrap_or_clamp(x + dx, nx, periodic);
+        for (int c = 0; c < C16; ++c)
+            out[((long long)s * C16 + c) * ncell + v] = (c < C) ? in[src * C + c] : (u16)0;
+    }
+}
+
+// Partial weight gradients.  Xs: VM input copies [3][MB 16][v]; dA: VM
+// output gradient [NB 16][v].  Workgroup b handles tap b / splits and the
+// b % splits-th share of the K range (rows z, y and 32-cell x blocks);
+// each wave writes its own partial [MB 16][NB 16].
+template <int MB, int NB>
+__global__ void __launch_bounds__(THREADS)
+wgrad_kernel(const u16* __restrict__ Xs, const u16* __restrict__ dA, float* __restrict__ partial,
+             int nx, int ny, int nz, int periodic, int splits)
+{
+    constexpr int CI16 = 16 * MB, CO16 = 16 * NB;
+    const int tap = blockIdx.x / splits, split = blockIdx.x % splits;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int xl = l & 15, grp = l >> 4;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const long long ncell = (long long)nx * ny * nz;
+    const int nxb = nx / 32;
+    const long long steps = (long long)nz * ny * nxb;
+    const long long parts = (long long)splits * 4;
+    const long long me = (long long)split * 4 + wave;
+    const long long beg = steps * me / parts, end = steps * (me + 1) / parts;
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const u16* xs_base = Xs + (long long)(dx + 1) * CI16 * ncell;
+    for (long long st = beg; st < end; ++st) {
+        const int xb = (int)(st % nxb);
+        const long long zy = st / nxb;
+        const int y = (int)(zy % ny), z = (int)(zy / ny);
+        const int zs = wrap_or_clamp(z + dz, nz, periodic), ys = wrap_or_clamp(y + dy, ny, periodic);
+        const long long xoff = 32 * xb + 8 * grp;
+        const long long vin = ((long long)zs * ny + ys) * nx + xoff;
+        const long long vout = ((long long)z * ny + y) * nx + xoff;
+        u32x4 a[MB], b[NB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) a[m] = *(const u32x4*)(xs_base + (16 * m + xl) * ncell + vin);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) b[n] = *(const u32x4*)(dA + (16 * n + xl) * ncell + vout);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = mfma(a[m], b[n], acc[m][n]);
+    }
+    // D[4 grp + i][xl] of block (m, n): input channel 16 m + 4 grp + i,
+    // output channel 16 n + xl
+    float* p = partial + ((long long)tap * parts + me) * CI16 * CO16;
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) p[(16 * m + 4 * grp + i) * CO16 + 16 * n + xl] = acc[m][n][i];
+}
+
+// Gradient of the master weights W[cout][cin][27]: sum of the partials of
+// every wave in a fixed order.
+__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int parts, int ci16, int co16,
+                                    int cin, int cout, float* __restrict__ gW)
+{
+    const int total = cout * cin * TAPS;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int tap = e % TAPS, ci = (e / TAPS) % cin, co = e / (TAPS * cin);
+        const float* p = partial + (long long)tap * parts * ci16 * co16 + ci * co16 + co;
+        float s = 0.0f;
+        for (int k = 0; k < parts; ++k) s += p[(long long)k * ci16 * co16];
+        gW[e] = s;
+    }
+}
+
+// Bias gradient: sums over cells of the VM BF16 output gradient dA[c][v];
+// workgroup (c, j) sums the j-th of BIAS_CHUNKS shares of channel c, then
+// one thread per channel adds the shares in order.
+constexpr int BIAS_CHUNKS = 64;
+
+__global__ void __launch_bounds__(THREADS)
+bias_partial_kernel(const u16* __restrict__ dA, long long ncell, float* __restrict__ part)
+{
+    __shared__ float red[THREADS];
+    const int c = blockIdx.x / BIAS_CHUNKS, j = blockIdx.x % BIAS_CHUNKS;
+    const long long beg = ncell * j / BIAS_CHUNKS, end = ncell * (j + 1) / BIAS_CHUNKS;
+    float s = 0.0f;
+    for (long long v = beg + threadIdx.x; v < end; v += THREADS) s += bf2f(dA[c * ncell + v]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void bias_final_kernel(const float* __restrict__ part, int C, float* __restrict__ gb)
+{
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    float s = 0.0f;
+    for (int j = 0; j < BIAS_CHUNKS; ++j) s += part[c * BIAS_CHUNKS + j];
+    gb[c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// input packing, targets, loss, optimizer
+// ---------------------------------------------------------------------------
+
+struct Norm {
+    float mu[NF], inv_sigma[NF];
+    double tau[NF], inv_tau[NF];
+};
+
+// head of an FP32 pair -> CL BF16 [v][8] of (U - mu) / sigma, channels 5..7 = 0
+__global__ void pack_input_kernel(const float* __restrict__ U, long long ncell, Norm nm,
+                                  u16* __restrict__ X)
+{
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * blockDim.x) {
+        u16 x[8];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) x[f] = f2bf((U[f * ncell + v] - nm.mu[f]) * nm.inv_sigma[f]);
+        x[5] = x[6] = x[7] = 0;
+        u32x4 w;
+        w[0] = x[0] | ((unsigned)x[1] << 16);
+        w[1] = x[2] | ((unsigned)x[3] << 16);
+        w[2] = x[4] | ((unsigned)x[5] << 16);
+        w[3] = x[6] | ((unsigned)x[7] << 16);
+        *(u32x4*)(X + v * 8) = w;
+    }
+}
+
+// mean of the 2x2x2 fine cells over coarse cell (x, y, z), field f, FP64
+__device__ __forceinline__ double restrict_cell(const double* __restrict__ fine, int f, int x,
+                                                int y, int z, int nx, int ny, int nz)
+{
+    const long long fx = 2LL * nx, fy = 2LL * ny, fz = 2LL * nz;
+    const double* p = fine + (long long)f * fx * fy * fz;
+    double s = 0.0;
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) s += p[((2LL * z + k) * fy + 2 * y + j) * fx + 2 * x + i];
+    return s * 0.125;
+}
+
+// mode 0: U = R(fine) as an FP32 pair; mode 1: target = (R(fine) - (head -
+// comp)) / tau
+__global__ void restrict_kernel(const double* __restrict__ fine, int nx, int ny, int nz, int mode,
+                                float* __restrict__ U, float* __restrict__ target, Norm nm)
+{
+    const long long ncell = (long long)nx * ny * nz;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+        for (int f = 0; f < NF; ++f) {
+            const double r = restrict_cell(fine, f, x, y, z, nx, ny, nz);
+            if (mode == 0) {
+                const float head = (float)r;
+                U[f * ncell + v] = head;
+                U[(NF + f) * ncell + v] = (float)((double)head - r);
+            } else {
+                const double u = (double)U[f * ncell + v] - (double)U[(NF + f) * ncell + v];
+                target[f * ncell + v] = (float)((r - u) * nm.inv_tau[f]);
+            }
+        }
+    }
+}
+
+// MSE loss partials (FP64, one per workgroup) and the output gradient
+// 2 (y - t) / N as BF16, CL [v][8] (channels 5..7 zero) and VM [16][v]
+// (channels 5..15 zero)
+__global__ void __launch_bounds__(THREADS)
+loss_kernel(const float* __restrict__ y, const float* __restrict__ t, long long ncell,
+            double* __restrict__ partial, u16* __restrict__ dCL, u16* __restrict__ dVM)
+{
+    __shared__ double red[THREADS];
+    const float scale = (float)(2.0 / (double)(ncell * NF));
+    double s = 0.0;
+    for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * THREADS) {
+        u16 d[8];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const float e = y[f * ncell + v] - t[f * ncell + v];
+            s += (double)e * (double)e;
+            d[f] = f2bf(scale * e);
+            dVM[f * ncell + v] = d[f];
+        }
+        d[5] = d[6] = d[7] = 0;
+        for (int f = NF; f < 16; ++f) dVM[f * ncell + v] = 0;
+        u32x4 w;
+        w[0] = d[0] | ((unsigned)d[1] << 16);
+        w[1] = d[2] | ((unsigned)d[3] << 16);
+        w[2] = d[4] | ((unsigned)d[5] << 16);
+        w[3] = d[6] | ((unsigned)d[7] << 16);
+        *(u32x4*)(dCL + v * 8) = w;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Adam (Kingma and Ba, Algorithm 1); c1 = 1 / (1 - beta1^t), c2 = 1 / (1 -
+// beta2^t)
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v2, int n, float lr, float c1, float c2)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v2[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v2[i] = vi;
+        p[i] = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// correction with fallback
+// ---------------------------------------------------------------------------
+
+struct CorrState {
+    double mean[NF];      // channel means of y
+    double moved[NF];     // total represented change per field
+    double mag[NF];       // sum of |change| per field
+    unsigned int bad;     // a corrected cell is non-physical
+    int applied, fallbacks;
+    int ok;               // decision of the last correction
+};
+
+// TwoSum accumulation of the channel sums of y, one partial pair per block
+__device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
+{
+    double t = s + x, bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
+__global__ void __launch_bounds__(THREADS)
+mean_partial_kernel(const float* __restrict__ y, long long ncell, double* __restrict__ partial)
+{
+    __shared__ double rs[NF][THREADS / 64], rc[NF][THREADS / 64];
+    double s[NF], c[NF];
+    for (int f = 0; f < NF; ++f) s[f] = c[f] = 0.0;
+    for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * THREADS)
+        for (int f = 0; f < NF; ++f) two_sum_add(s[f], c[f], (double)y[f * ncell + v]);
+    for (int f = 0; f < NF; ++f) {
+        for (int off = 32; off > 0; off >>= 1) {
+            double s2 = __shfl_xor(s[f], off), c2 = __shfl_xor(c[f], off);
+            two_sum_add(s[f], c[f], s2);
+            c[f] += c2;
+        }
+        if ((threadIdx.x & 63) == 0) {
+            rs[f][threadIdx.x >> 6] = s[f];
+            rc[f][threadIdx.x >> 6] = c[f];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NF) {
+        const int f = threadIdx.x;
+        double S = 0.0, C = 0.0;
+        for (int w = 0; w < THREADS / 64; ++w) {
+            two_sum_add(S, C, rs[f][w]);
+            C += rc[f][w];
+        }
+        partial[blockIdx.x * NF + f] = S + C;
+    }
+}
+
+__global__ void mean_final_kernel(const double* __restrict__ partial, int n, long long ncell,
+                                  CorrState* __restrict__ cs)
+{
+    if (threadIdx.x < NF) {
+        const int f = threadIdx.x;
+        double S = 0.0, C = 0.0;
+        for (int b = 0; b < n; ++b) two_sum_add(S, C, partial[b * NF + f]);
+        cs->mean[f] = (S + C) / (double)ncell;
+        cs->moved[f] = 0.0;
+        cs->mag[f] = 0.0;
+    }
+    if (threadIdx.x == 0) cs->bad = 0u;
+}
+
+// Candidate corrected pair (Kahan sum of delta into head/comp), positivity
+// of every candidate cell (FP64 primitive recovery), and per-block sums of
+// the represented change and of its magnitude.
+__global__ void __launch_bounds__(THREADS)
+apply_kernel(const float* __restrict__ U, const float* __restrict__ y, long long ncell, Norm nm,
+             gs::Phys k, const CorrState* csr, float* __restrict__ cand,
+             double* __restrict__ partial, CorrState* cs)
+{
+    __shared__ double red[2 * NF][THREADS];
+    double moved[NF], mag[NF];
+    for (int f = 0; f < NF; ++f) moved[f] = mag[f] = 0.0;
+    bool bad = false;
+    for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * THREADS) {
+        double u[NF], w[NF];
+        for (int f = 0; f < NF; ++f) {
+            const float head = U[f * ncell + v], comp = U[(NF + f) * ncell + v];
+            const float d = (float)(nm.tau[f] * ((double)y[f * ncell + v] - csr->mean[f]));
+            const float yy = d - comp;
+            const float s = head + yy;
+            const float c2 = (s - head) - yy;
+            cand[f * ncell + v] = s;
+            cand[(NF + f) * ncell + v] = c2;
+            const double change = ((double)s - (double)c2) - ((double)head - (double)comp);
+            moved[f] += change;
+            mag[f] += fabs(change);
+            u[f] = (double)s - (double)c2;
+        }
+        bad |= !gs::cons_to_prim(u, w, k);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&cs->bad, 1u);
+    for (int f = 0; f < NF; ++f) {
+        red[2 * f][threadIdx.x] = moved[f];
+        red[2 * f + 1][threadIdx.x] = mag[f];
+    }
+    __syncthreads();
+    for (int w = THREADS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int q = 0; q < 2 * NF; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 2 * NF) partial[blockIdx.x * 2 * NF + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// decision: accept unless non-physical, or some |total change| exceeds
+// 1e-5 of the change's magnitude plus 1e-30 (also false for NaN)
+__global__ void decide_kernel(const double* __restrict__ partial, int n, CorrState* __restrict__ cs)
+{
+    if (threadIdx.x != 0) return;
+    bool ok = cs->bad == 0u;
+    for (int f = 0; f < NF; ++f) {
+        double moved = 0.0, mag = 0.0;
+        for (int b = 0; b < n; ++b) {
+            moved += partial[b * 2 * NF + 2 * f];
+            mag += partial[b * 2 * NF + 2 * f + 1];
+        }
+        cs->moved[f] = moved;
+        cs->mag[f] = mag;
+        ok = ok && (fabs(moved) <= 1e-5 * mag + 1e-30);
+    }
+    cs->ok = ok ? 1 : 0;
+    if (ok)
+        cs->applied += 1;
+    else
+        cs->fallbacks += 1;
+}
+
+__global__ void commit_kernel(const float* __restrict__ cand, long long n, const CorrState* __restrict__ cs,
+                              float* __restrict__ U)
+{
+    if (!cs->ok) return;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        U[i] = cand[i];
+}
+
+__global__ void init_corr_kernel(CorrState* cs)
+{
+    for (int f = 0; f < NF; ++f) cs->mean[f] = cs->moved[f] = cs->mag[f] = 0.0;
+    cs->bad = 0u;
+    cs->applied = cs->fallbacks = 0;
+    cs->ok = 0;
+}
+
+__global__ void zero_floats_kernel(float* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+}  // namespace gsc
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+using namespace gsc;
+
+namespace {
+
+thread_local std::string g_cnn_create_error;
+
+constexpr int RED_BLOCKS = 512;
+constexpr int WG_SPLITS = 64;  // workgroups per tap in the weight gradient
+
+}  // namespace
+
+struct gs_cnn {
+    int nx, ny, nz, bc;
+    double gamma;
+    hipStream_t stream;
+    std::string err;
+    long long ncell;
+    Norm norm;
+    int step;  // Adam step count
+    // parameters, gradients, moments (FP32)
+    float *P, *G, *M, *V;
+    // packed weights: forward l1, l2, l3; backward (mirrored) l2, l3
+    u16 *wf1, *wf2, *wf3, *wb2, *wb3;
+    // activations (CL): input x (8), h1, h2 (32); output y, FP32 SoA
+    u16 *x, *h1, *h2;
+    float* y;
+    // training: gradients dY (CL 8, VM 16), dA2, dA1 (CL 32, VM 32), VM
+    // shifted copies of x (16 ch), h1, h2 (32 ch)
+    u16 *dY, *dYv, *dA2, *dA2v, *dA1, *dA1v, *xs, *h1s, *h2s;
+    float* wpart;   // weight-gradient partials
+    float* bpart;   // bias-gradient partials
+    double* red;    // reduction partials
+    double* host_red;
+    float* cand;    // corrected candidate pair
+    CorrState* cs;
+    CorrState* host_cs;
+};
+
+namespace {
+
+int cfail(gs_cnn* h, int code, const std::string& msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_cnn_create_error = msg;
+    return code;
+}
+
+int chip(gs_cnn* h, hipError_t e, const char* what)
+{
+    return cfail(h, GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int grid_for(long long n, int per = THREADS, int cap = 4096)
+{
+    long long b = (n + per - 1) / per;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+ConvGeom conv_geom(const gs_cnn* h)
+{
+    ConvGeom g;
+    g.nx = h->nx;
+    g.ny = h->ny;
+    g.nz = h->nz;
+    g.periodic = h->bc == GS_BC_PERIODIC;
+    g.ntx = (h->nx + 15) / 16;
+    g.nty = (h->ny + 15) / 16;
+    const int ntile = g.ntx * g.nty;
+    // aim for >= 2048 workgroups, at least one plane each
+    long long want = (2048 + ntile - 1) / ntile;
+    int kz = (int)((h->nz + want - 1) / want);
+    g.kz = kz < 1 ? 1 : kz;
+    return g;
+}
+
+int conv_blocks(const ConvGeom& g) { return g.ntx * g.nty * ((g.nz + g.kz - 1) / g.kz); }
+
+hipError_t pack_all(gs_cnn* h)
+{
+    const int blocks = 64;
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(THREADS), 0, h->stream, h->P + W1_OFF,
+                       NF, HID, 8, 2, 7, 0, h->wf1);
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(THREADS), 0, h->stream, h->P + W2_OFF,
+                       HID, HID, 32, 2, TAPS, 0, h->wf2);
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(THREADS), 0, h->stream, h->P + W3_OFF,
+                       HID, NF, 32, 1, TAPS, 0, h->wf3);
+    // mirrored: layer 2 (in 32 -> out 32), layer 3 (in: 5 gradient channels
+    // padded to 8 -> out 32)
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(THREADS), 0, h->stream, h->P + W2_OFF,
+                       HID, HID, 32, 2, TAPS, 1, h->wb2);
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(THREADS), 0, h->stream, h->P + W3_OFF,
+                       HID, NF, 8, 2, 7, 1, h->wb3);
+    return hipGetLastError();
+}
+
+// forward pass from the head of U; keeps x, h1, h2; writes y
+hipError_t forward(gs_cnn* h, const float* U)
+{
+    const ConvGeom g = conv_geom(h);
+    const int nb = conv_blocks(g);
+    hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(h->ncell)), dim3(THREADS), 0, h->stream, U,
+                       h->ncell, h->norm, h->x);
+    hipLaunchKernelGGL((conv_kernel<8, 2, EPI_RELU_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
+                       h->x, h->wf1, h->P + B1_OFF, (void*)h->h1, (const u16*)nullptr, g, HID);
+    hipLaunchKernelGGL((conv_kernel<32, 2, EPI_RELU_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
+                       h->h1, h->wf2, h->P + B2_OFF, (void*)h->h2, (const u16*)nullptr, g, HID);
+    hipLaunchKernelGGL((conv_kernel<32, 1, EPI_F32_SOA>), dim3(nb), dim3(THREADS), 0, h->stream,
+                       h->h2, h->wf3, h->P + B3_OFF, (void*)h->y, (const u16*)nullptr, g, NF);
+    return hipGetLastError();
+}
+
+void bias_grad(gs_cnn* h, const u16* dAv, int C, float* gb)
+{
+    hipLaunchKernelGGL(bias_partial_kernel, dim3(C * BIAS_CHUNKS), dim3(THREADS), 0, h->stream, dAv,
+                       h->ncell, h->bpart);
+    hipLaunchKernelGGL(bias_final_kernel, dim3(1), dim3(64), 0, h->stream, h->bpart, C, gb);
+}
+
+// loss and all parameter gradients into G (after forward); loss partials in
+// red[0 .. RED_BLOCKS)
+hipError_t backward(gs_cnn* h, const float* target)
+{
+    const ConvGeom g = conv_geom(h);
+    const int nb = conv_blocks(g);
+    const long long n = h->ncell;
+    hipLaunchKernelGGL(loss_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, target, n,
+                       h->red, h->dY, h->dYv);
+    // layer 3: dW3 from h2 and dY; dH2 = conv(dY, mirrored W3) masked by h2
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->h2, HID,
+                       HID, 3, h->nx, h->ny, h->nz, 1, h->h2s);
+    const int parts = WG_SPLITS * 4;
+    hipLaunchKernelGGL((wgrad_kernel<2, 1>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
+                       h->h2s, h->dYv, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W3_N)), dim3(THREADS), 0, h->stream,
+                       h->wpart, parts, 32, 16, HID, NF, h->G + W3_OFF);
+    bias_grad(h, h->dYv, NF, h->G + B3_OFF);
+    hipLaunchKernelGGL((conv_kernel<8, 2, EPI_MASK_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
+                       h->dY, h->wb3, (const float*)nullptr, (void*)h->dA2, h->h2, g, HID);
+    // layer 2
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA2, HID, HID,
+                       1, h->nx, h->ny, h->nz, 1, h->dA2v);
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->h1, HID,
+                       HID, 3, h->nx, h->ny, h->nz, 1, h->h1s);
+    hipLaunchKernelGGL((wgrad_kernel<2, 2>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
+                       h->h1s, h->dA2v, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W2_N)), dim3(THREADS), 0, h->stream,
+                       h->wpart, parts, 32, 32, HID, HID, h->G + W2_OFF);
+    bias_grad(h, h->dA2v, HID, h->G + B2_OFF);
+    hipLaunchKernelGGL((conv_kernel<32, 2, EPI_MASK_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
+                       h->dA2, h->wb2, (const float*)nullptr, (void*)h->dA1, h->h1, g, HID);
+    // layer 1
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA1, HID, HID,
+                       1, h->nx, h->ny, h->nz, 1, h->dA1v);
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->x, 8, 16,
+                       3, h->nx, h->ny, h->nz, 1, h->xs);
+    hipLaunchKernelGGL((wgrad_kernel<1, 2>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
+                       h->xs, h->dA1v, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W1_N)), dim3(THREADS), 0, h->stream,
+                       h->wpart, parts, 16, 32, NF, HID, h->G + W1_OFF);
+    bias_grad(h, h->dA1v, HID, h->G + B1_OFF);
+    return hipGetLastError();
+}
+
+int read_loss(gs_cnn* h, double* loss)
+{
+    hipError_t e = hipMemcpyAsync(h->host_red, h->red, RED_BLOCKS * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return chip(h, e, "loss read-back");
+    double s = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) s += h->host_red[b];
+    *loss = s / (double)(h->ncell * NF);
+    return GS_OK;
+}
+
+int check_train(gs_cnn* h, const void* U, const void* target)
+{
+    if (!U || !target || !aligned16(U) || !aligned16(target))
+        return cfail(h, GS_ERR_ARG, "U or target is NULL or not 16-byte aligned");
+    if (h->bc != GS_BC_PERIODIC)
+        return cfail(h, GS_ERR_ARG, "training needs periodic boundaries");
+    if (h->nx % 32 != 0) return cfail(h, GS_ERR_ARG, "training needs nx to be a multiple of 32");
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_cnn_param_count(void) { return P_N; }
+
+int gs_cnn_create(int nx, int ny, int nz, int bc, double gamma, void* stream, gs_cnn** out)
+{
+    g_cnn_create_error.clear();
+    if (!out) return cfail(nullptr, GS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return cfail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
+    if ((long long)nx * ny * nz > (1LL << 28)) return cfail(nullptr, GS_ERR_ARG, "mesh too large");
+    if (bc != GS_BC_OUTFLOW && bc != GS_BC_PERIODIC)
+        return cfail(nullptr, GS_ERR_ARG, "unknown boundary kind");
+    if (!std::isfinite(gamma) || !(gamma > 1.0)) return cfail(nullptr, GS_ERR_ARG, "gamma must be > 1");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return chip(nullptr, e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return chip(nullptr, e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return cfail(nullptr, GS_ERR_HIP, std::string("built for gfx950, device is ") + prop.gcnArchName);
+
+    gs_cnn* h = new gs_cnn();
+    std::memset((void*)&h->norm, 0, sizeof(Norm));
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->bc = bc;
+    h->gamma = gamma;
+    h->stream = (hipStream_t)stream;
+    h->ncell = (long long)nx * ny * nz;
+    h->step = 0;
+    for (int f = 0; f < NF; ++f) {
+        h->norm.mu[f] = 0.0f;
+        h->norm.inv_sigma[f] = 1.0f;
+        h->norm.tau[f] = 1.0;
+        h->norm.inv_tau[f] = 1.0;
+    }
+    const long long n = h->ncell;
+    struct Alloc {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&h->P, P_N * 4}, {(void**)&h->G, P_N * 4}, {(void**)&h->M, P_N * 4},
+        {(void**)&h->V, P_N * 4},
+        {(void**)&h->wf1, 7 * 2 * 1024}, {(void**)&h->wf2, TAPS * 2 * 1024},
+        {(void**)&h->wf3, TAPS * 1 * 1024}, {(void**)&h->wb2, TAPS * 2 * 1024},
+        {(void**)&h->wb3, 7 * 2 * 1024},
+        {(void**)&h->x, (size_t)n * 8 * 2}, {(void**)&h->h1, (size_t)n * 32 * 2},
+        {(void**)&h->h2, (size_t)n * 32 * 2}, {(void**)&h->y, (size_t)n * NF * 4},
+        {(void**)&h->dY, (size_t)n * 8 * 2}, {(void**)&h->dYv, (size_t)n * 16 * 2},
+        {(void**)&h->dA2, (size_t)n * 32 * 2}, {(void**)&h->dA2v, (size_t)n * 32 * 2},
+        {(void**)&h->dA1, (size_t)n * 32 * 2}, {(void**)&h->dA1v, (size_t)n * 32 * 2},
+        {(void**)&h->xs, (size_t)n * 3 * 16 * 2}, {(void**)&h->h1s, (size_t)n * 3 * 32 * 2},
+        {(void**)&h->h2s, (size_t)n * 3 * 32 * 2},
+        {(void**)&h->wpart, (size_t)TAPS * WG_SPLITS * 4 * 32 * 32 * 4},
+        {(void**)&h->bpart, (size_t)32 * BIAS_CHUNKS * 4},
+        {(void**)&h->red, RED_BLOCKS * 2 * NF * 8}, {(void**)&h->cand, (size_t)n * 2 * NF * 4},
+        {(void**)&h->cs, sizeof(CorrState)},
+    };
+    for (auto& a : allocs) *a.p = nullptr;
+    h->host_red = nullptr;
+    h->host_cs = nullptr;
+    for (auto& a : allocs) {
+        if ((e = hipMalloc(a.p, a.bytes)) != hipSuccess) {
+            int r = chip(nullptr, e, "allocation");
+            gs_cnn_destroy(h);
+            return r;
+        }
+    }
+    if ((e = hipHostMalloc((void**)&h->host_red, RED_BLOCKS * 2 * NF * 8, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc((void**)&h->host_cs, sizeof(CorrState), hipHostMallocDefault)) != hipSuccess) {
+        int r = chip(nullptr, e, "pinned allocation");
+        gs_cnn_destroy(h);
+        return r;
+    }
+    hipLaunchKernelGGL(zero_floats_kernel, dim3(64), dim3(THREADS), 0, h->stream, h->P, P_N);
+    hipLaunchKernelGGL(zero_floats_kernel, dim3(64), dim3(THREADS), 0, h->stream, h->M, P_N);
+    hipLaunchKernelGGL(zero_floats_kernel, dim3(64), dim3(THREADS), 0, h->stream, h->V, P_N);
+    hipLaunchKernelGGL(init_corr_kernel, dim3(1), dim3(1), 0, h->stream, h->cs);
+    e = pack_all(h);
+    if (e != hipSuccess) {
+        int r = chip(nullptr, e, "init kernels");
+        gs_cnn_destroy(h);
+        return r;
+    }
+    *out = h;
+    return GS_OK;
+}
+
+int gs_cnn_set_params(gs_cnn* h, const float* host_params)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!host_params) return cfail(h, GS_ERR_ARG, "params is NULL");
+    hipError_t e = hipMemcpyAsync(h->P, host_params, P_N * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return chip(h, e, "parameter upload");
+    hipLaunchKernelGGL(zero_floats_kernel, dim3(64), dim3(THREADS), 0, h->stream, h->M, P_N);
+    hipLaunchKernelGGL(zero_floats_kernel, dim3(64), dim3(THREADS), 0, h->stream, h->V, P_N);
+    h->step = 0;
+    e = pack_all(h);
+    return e == hipSuccess ? GS_OK : chip(h, e, "pack");
+}
+
+int gs_cnn_get_params(gs_cnn* h, float* host_params)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!host_params) return cfail(h, GS_ERR_ARG, "params is NULL");
+    hipError_t e = hipMemcpyAsync(host_params, h->P, P_N * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? GS_OK : chip(h, e, "parameter download");
+}
+
+int gs_cnn_set_norm(gs_cnn* h, const double* mu, const double* sigma, const double* tau)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!mu || !sigma || !tau) return cfail(h, GS_ERR_ARG, "NULL array");
+    for (int f = 0; f < NF; ++f) {
+        if (!std::isfinite(mu[f]) || !(sigma[f] > 0.0) || !std::isfinite(sigma[f]) || !(tau[f] > 0.0) ||
+            !std::isfinite(tau[f]))
+            return cfail(h, GS_ERR_ARG, "mu must be finite, sigma and tau finite and > 0");
+    }
+    for (int f = 0; f < NF; ++f) {
+        h->norm.mu[f] = (float)mu[f];
+        h->norm.inv_sigma[f] = (float)(1.0 / sigma[f]);
+        h->norm.tau[f] = tau[f];
+        h->norm.inv_tau[f] = 1.0 / tau[f];
+    }
+    return GS_OK;
+}
+
+int gs_cnn_forward(gs_cnn* h, const void* U, float* y)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!U || !y || !aligned16(U) || !aligned16(y))
+        return cfail(h, GS_ERR_ARG, "U or y is NULL or not 16-byte aligned");
+    hipError_t e = forward(h, (const float*)U);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(y, h->y, (size_t)h->ncell * NF * 4, hipMemcpyDeviceToDevice, h->stream);
+    return e == hipSuccess ? GS_OK : chip(h, e, "forward");
+}
+
+int gs_cnn_restrict(gs_cnn* h, const double* fine, void* U)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!fine || !U || !aligned16(fine) || !aligned16(U))
+        return cfail(h, GS_ERR_ARG, "fine or U is NULL or not 16-byte aligned");
+    hipLaunchKernelGGL(restrict_kernel, dim3(grid_for(h->ncell)), dim3(THREADS), 0, h->stream, fine,
+                       h->nx, h->ny, h->nz, 0, (float*)U, (float*)nullptr, h->norm);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GS_OK : chip(h, e, "restrict");
+}
+
+int gs_cnn_make_target(gs_cnn* h, const double* fine, const void* U, float* target)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!fine || !U || !target || !aligned16(fine) || !aligned16(U) || !aligned16(target))
+        return cfail(h, GS_ERR_ARG, "NULL or misaligned pointer");
+    hipLaunchKernelGGL(restrict_kernel, dim3(grid_for(h->ncell)), dim3(THREADS), 0, h->stream, fine,
+                       h->nx, h->ny, h->nz, 1, (float*)U, target, h->norm);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GS_OK : chip(h, e, "target");
+}
+
+int gs_cnn_gradients(gs_cnn* h, const void* U, const float* target, float* host_grads, double* loss)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    int r = check_train(h, U, target);
+    if (r != GS_OK) return r;
+    if (!host_grads || !loss) return cfail(h, GS_ERR_ARG, "output is NULL");
+    hipError_t e = forward(h, (const float*)U);
+    if (e == hipSuccess) e = backward(h, target);
+    if (e != hipSuccess) return chip(h, e, "gradients");
+    r = read_loss(h, loss);
+    if (r != GS_OK) return r;
+    e = hipMemcpy(host_grads, h->G, P_N * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? GS_OK : chip(h, e, "gradient download");
+}
+
+int gs_cnn_train_step(gs_cnn* h, const void* U, const float* target, float lr, double* loss)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    int r = check_train(h, U, target);
+    if (r != GS_OK) return r;
+    if (!std::isfinite(lr) || !(lr > 0.0f)) return cfail(h, GS_ERR_ARG, "lr must be finite and > 0");
+    hipError_t e = forward(h, (const float*)U);
+    if (e == hipSuccess) e = backward(h, target);
+    if (e != hipSuccess) return chip(h, e, "train step");
+    if (loss) {
+        r = read_loss(h, loss);
+        if (r != GS_OK) return r;
+    }
+    h->step += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, h->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, h->step)));
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(P_N)), dim3(THREADS), 0, h->stream, h->P, h->G,
+                       h->M, h->V, P_N, lr, c1, c2);
+    e = pack_all(h);
+    return e == hipSuccess ? GS_OK : chip(h, e, "adam");
+}
+
+int gs_cnn_correct(gs_cnn* h, void* U)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!U || !aligned16(U)) return cfail(h, GS_ERR_ARG, "U is NULL or not 16-byte aligned");
+    const long long n = h->ncell;
+    hipError_t e = forward(h, (const float*)U);
+    if (e != hipSuccess) return chip(h, e, "correct: forward");
+    gs::Phys k;
+    k.gamma = h->gamma;
+    k.gm1 = h->gamma - 1.0;
+    k.inv_gm1 = 1.0 / (h->gamma - 1.0);
+    for (int d = 0; d < 3; ++d) k.inv_h[d] = 1.0;
+    k.cfl = 1.0;
+    hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, n,
+                       h->red);
+    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, h->stream, h->red, RED_BLOCKS, n, h->cs);
+    hipLaunchKernelGGL(apply_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
+                       h->y, n, h->norm, k, h->cs, h->cand, h->red, h->cs);
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, h->stream, h->red, RED_BLOCKS, h->cs);
+    hipLaunchKernelGGL(commit_kernel, dim3(grid_for(n * 2 * NF)), dim3(THREADS), 0, h->stream, h->cand,
+                       n * 2 * NF, h->cs, (float*)U);
+    e = hipGetLastError();
+    return e == hipSuccess ? GS_OK : chip(h, e, "correct");
+}
+
+int gs_cnn_counts(gs_cnn* h, int* applied, int* fallbacks)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!applied || !fallbacks) return cfail(h, GS_ERR_ARG, "output is NULL");
+    hipError_t e = hipMemcpyAsync(h->host_cs, h->cs, sizeof(CorrState), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return chip(h, e, "counts");
+    *applied = h->host_cs->applied;
+    *fallbacks = h->host_cs->fallbacks;
+    return GS_OK;
+}
+
+int gs_cnn_set_stream(gs_cnn* h, void* stream)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    h->stream = (hipStream_t)stream;
+    return GS_OK;
+}
+
+void gs_cnn_destroy(gs_cnn* h)
+{
+    if (!h) return;
+    void* ps[] = {h->P, h->G, h->M, h->V, h->wf1, h->wf2, h->wf3, h->wb2, h->wb3, h->x, h->h1,
+                  h->h2, h->y, h->dY, h->dYv, h->dA2, h->dA2v, h->dA1, h->dA1v, h->xs, h->h1s,
+                  h->h2s, h->wpart, h->bpart, h->red, h->cand, h->cs};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    if (h->host_red) (void)hipHostFree(h->host_red);
+    if (h->host_cs) (void)hipHostFree(h->host_cs);
+    delete h;
+}
+
+const char* gs_cnn_last_error(const gs_cnn* h)
+{
+    return h ? h->err.c_str() : g_cnn_create_error.c_str();
+}
+
+}  // extern "C"

@@ -9,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gs_fluid.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("gs_fluid.h", "gs_cnn.h")]
 
 lib_mod = pytest.importorskip("paper_1812_07977_amd._lib")
 
@@ -22,9 +22,12 @@ def _lib():
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gs_fluid_\w+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(gs_(?:fluid|cnn)_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_signatures():

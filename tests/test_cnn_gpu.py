@@ -1,0 +1,282 @@
+"""GPU tests of the learned-correction kernels against the CPU oracle
+(oracle/cnn.py), through the C ABI (include/gs_cnn.h).
+
+The GPU multiplies BF16 operands and accumulates in FP32.  The oracle is
+handed exactly the operands the GPU sees (weights and activations rounded to
+BF16 between layers, oracle.cnn.bf16_round) and computes in FP64:
+  - with dyadic weights and inputs chosen so that every product and partial
+    sum is exact in FP32, the two sides must agree bit for bit, whatever the
+    summation order (forward pass);
+  - with ordinary random values, FP32 and FP64 sums differ by at most about
+    K u sum |terms| (K terms, u = 2^-24), and where that straddles a BF16
+    rounding boundary of a hidden activation the two sides round it one
+    BF16 unit apart; the tests bound both effects from absolute values
+    computed by the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn as ocnn
+
+pytestmark = pytest.mark.gpu
+
+HIDDEN_CH = 32
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _net(shape, bc="periodic"):
+    from paper_1812_07977_amd.learned import CorrectionNet
+    return CorrectionNet(shape, bc=bc)
+
+
+def _pair(head):
+    """An FP32 state pair with the given head and zero compensation."""
+    import torch
+    h = torch.from_numpy(np.ascontiguousarray(head, dtype=np.float32))
+    return torch.stack([h, torch.zeros_like(h)]).contiguous().cuda()
+
+
+def _oracle_forward_bf16(x, params, bc):
+    """The network with the GPU's roundings: BF16 weights, BF16 activations
+    after each ReLU, FP64 sums."""
+    (w1, b1), (w2, b2), (w3, b3) = params
+    r = ocnn.bf16_round
+    a1 = ocnn.conv3(x, r(w1), b1, bc)
+    h1 = r(ocnn.relu(a1))
+    a2 = ocnn.conv3(h1, r(w2), b2, bc)
+    h2 = r(ocnn.relu(a2))
+    y = ocnn.conv3(h2, r(w3), b3, bc)
+    return y, (a1, h1, a2, h2)
+
+
+def _params_from_flat(flat):
+    from paper_1812_07977_amd.learned import split_params
+    p = [a.astype(np.float64) for a in split_params(flat)]
+    return [(p[0], p[1]), (p[2], p[3]), (p[4], p[5])]
+
+
+def _dyadic_params(rng):
+    """Sparse weights in {0, +-1/8} (density 0.2 in the first layer, 0.1 after)
+    and biases in multiples of 1/16, so every
+    sum of the network is exact in FP32."""
+    from paper_1812_07977_amd.learned import SHAPES
+    parts = []
+    for k, s in enumerate(SHAPES):
+        if len(s) == 1:
+            parts.append(rng.integers(-4, 5, s) / 16.0)
+        else:
+            dens = 0.2 if k == 0 else 0.1
+            w = rng.choice([-0.125, 0.125], s) * (rng.random(s) < dens)
+            parts.append(w)
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,bc", [((32, 16, 8), "periodic"), ((20, 12, 6), "outflow"),
+                                      ((16, 16, 16), "periodic")])
+def test_forward_is_bit_exact_on_exactly_representable_data(shape, bc):
+    nx, ny, nz = shape
+    _say(f"case: cnn forward dyadic {shape} {bc}")
+    rng = np.random.default_rng(10)
+    flat = _dyadic_params(rng)
+    head = rng.integers(-8, 9, (5, nz, ny, nx)) / 8.0
+    with _net(shape, bc) as N:
+        N.set_params(flat)
+        y = N.forward(_pair(head)).cpu().numpy().astype(np.float64)
+    obc = ocnn.PERIODIC if bc == "periodic" else ocnn.OUTFLOW
+    ref, (_, h1, _, h2) = _oracle_forward_bf16(head, _params_from_flat(flat), obc)
+    assert np.count_nonzero(h1) > 0.2 * h1.size and np.count_nonzero(h2) > 0.2 * h2.size
+    assert np.array_equal(y, ref)
+
+
+def test_forward_random_weights_within_fp32_accumulation_bound():
+    shape = (32, 16, 12)
+    nx, ny, nz = shape
+    from paper_1812_07977_amd.learned import init_params
+    rng = np.random.default_rng(11)
+    flat = init_params(3, out_scale=1.0)
+    flat[-5:] = rng.standard_normal(5)
+    head = 1.0 + 0.3 * rng.standard_normal((5, nz, ny, nx))
+    mu, sigma = np.full(5, 1.0), np.full(5, 0.3)
+    with _net(shape) as N:
+        N.set_params(flat)
+        N.set_norm(mu, sigma, np.ones(5))
+        y = N.forward(_pair(head)).cpu().numpy().astype(np.float64)
+    # the GPU's input: (head - mu) / sigma in FP32, rounded to BF16
+    h32 = head.astype(np.float32)
+    x = ocnn.bf16_round(((h32 - np.float32(1.0)) * np.float32(1.0 / 0.3)).astype(np.float64))
+    params = _params_from_flat(flat)
+    ref, (a1, h1, a2, h2) = _oracle_forward_bf16(x, params, ocnn.PERIODIC)
+    # Where an FP32 and an FP64 sum straddle a BF16 rounding boundary the two
+    # sides round a hidden activation to neighbouring BF16 values, at most
+    # one BF16 unit (2^-8 |h|) apart, and the difference propagates through
+    # the later layers.  Bound, from absolute values: E1 = 2^-8 |h1|,
+    # E2 = 2^-8 |h2| + |W2| * E1, and for y: |W3| * E2 plus the FP32
+    # accumulation error of the last layer, 1e-5 of its absolute sums.
+    r = ocnn.bf16_round
+    w2, w3 = r(params[1][0]), r(params[2][0])
+    z2, z3 = np.zeros(HIDDEN_CH), np.zeros(5)
+    e1 = 2.0 ** -8 * np.abs(h1)
+    e2 = 2.0 ** -8 * np.abs(h2) + ocnn.conv3(e1, np.abs(w2), z2, ocnn.PERIODIC)
+    absum = ocnn.conv3(np.abs(h2), np.abs(w3), np.abs(params[2][1]), ocnn.PERIODIC)
+    bound = ocnn.conv3(e2, np.abs(w3), z3, ocnn.PERIODIC) + 1e-5 * absum
+    err = np.abs(y - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    # and typically far inside it
+    assert np.median(err / absum) < 1e-3
+
+
+def test_gradients_match_the_oracle():
+    shape = (32, 8, 8)
+    nx, ny, nz = shape
+    _say("case: cnn gradients 32x8x8 periodic")
+    from paper_1812_07977_amd.learned import split_params
+    import torch
+    rng = np.random.default_rng(12)
+    flat = _dyadic_params(rng)
+    head = rng.integers(-8, 9, (5, nz, ny, nx)) / 8.0
+    with _net(shape) as N:
+        N.set_params(flat)
+        U = _pair(head)
+        params = _params_from_flat(flat)
+        y, cache = _oracle_forward_bf16(head, params, ocnn.PERIODIC)
+        # a target whose error y - t is exactly representable in BF16
+        e = rng.integers(-8, 9, y.shape) / 8.0
+        t = (y - e).astype(np.float32)
+        assert np.array_equal(t.astype(np.float64), y - e)
+        loss, g = N.gradients(U, torch.from_numpy(t).cuda())
+    # oracle: the loss gradient 2 e / N is exact in BF16 (N a power of 2 times
+    # 5 is not, so round it as the GPU does)
+    n = e.size
+    dy = ocnn.bf16_round(np.float32(2.0 / n) * e.astype(np.float32))
+    assert loss == pytest.approx(np.mean(e * e), rel=1e-12)
+    # backward with the GPU's roundings: gradients of the hidden layers are
+    # rounded to BF16 before they are used
+    (w1, b1), (w2, b2), (w3, b3) = params
+    r = ocnn.bf16_round
+    a1, h1, a2, h2 = cache
+    dw3, db3, dh2 = ocnn.conv3_backward(h2, r(w3), dy, ocnn.PERIODIC)
+    da2 = r(dh2 * (h2 > 0))
+    dw2, db2, dh1 = ocnn.conv3_backward(h1, r(w2), da2, ocnn.PERIODIC)
+    da1 = r(dh1 * (h1 > 0))
+    dw1, db1, _ = ocnn.conv3_backward(head, r(w1), da1, ocnn.PERIODIC)
+    # scales: the same sums over absolute values
+    aw3, ab3, _ = ocnn.conv3_backward(np.abs(h2), np.abs(r(w3)), np.abs(dy), ocnn.PERIODIC)
+    aw2, ab2, _ = ocnn.conv3_backward(np.abs(h1), np.abs(r(w2)), np.abs(da2), ocnn.PERIODIC)
+    aw1, ab1, _ = ocnn.conv3_backward(np.abs(head), np.abs(r(w1)), np.abs(da1), ocnn.PERIODIC)
+    got = split_params(g.astype(np.float64))
+    # FP32 sums over the cells: at most n u of the sum of absolute terms
+    tol = 1.5 * head[0].size * 2.0 ** -24
+    for name, gg, ref, sc in [("W1", got[0], dw1, aw1), ("b1", got[1], db1, ab1),
+                              ("W2", got[2], dw2, aw2), ("b2", got[3], db2, ab2),
+                              ("W3", got[4], dw3, aw3), ("b3", got[5], db3, ab3)]:
+        err = np.abs(gg - ref)
+        assert np.all(err <= tol * sc + 1e-30), (name, float(np.max(err / (sc + 1e-300))))
+        assert np.max(np.abs(ref)) > 0, name
+
+
+def test_adam_step_matches_the_oracle():
+    shape = (32, 8, 8)
+    nx, ny, nz = shape
+    import torch
+    from paper_1812_07977_amd.learned import init_params
+    rng = np.random.default_rng(13)
+    flat = init_params(4)
+    head = 1.0 + 0.2 * rng.standard_normal((5, nz, ny, nx))
+    t = torch.from_numpy((0.1 * rng.standard_normal((5, nz, ny, nx))).astype(np.float32)).cuda()
+    with _net(shape) as N:
+        N.set_params(flat)
+        U = _pair(head)
+        _, g = N.gradients(U, t)
+        N.train_step(U, t, 1e-3)
+        new = N.get_params()
+    ref, _, _ = ocnn.adam(flat.astype(np.float64), g.astype(np.float64), np.zeros(flat.size),
+                          np.zeros(flat.size), 1, lr=1e-3)
+    assert np.max(np.abs(new - ref)) <= 1e-6 * 1e-3 + 1e-7 * np.max(np.abs(flat))
+
+
+def test_restriction_and_target_match_the_oracle():
+    import torch
+    rng = np.random.default_rng(14)
+    fine = 1.0 + 0.5 * rng.random((5, 16, 12, 40))
+    with _net((20, 6, 8)) as N:
+        tau = np.array([0.5, 0.25, 2.0, 1.0, 4.0])
+        N.set_norm(np.zeros(5), np.ones(5), tau)
+        F = torch.from_numpy(fine).cuda()
+        U = N.restrict(F)
+        pair = U.cpu().numpy().astype(np.float64)
+        R = ocnn.restrict2(fine)
+        assert np.array_equal(pair[0], R.astype(np.float32).astype(np.float64))
+        # the compensation is itself FP32: the pair holds R to about 2^-48
+        assert np.max(np.abs(pair[0] - pair[1] - R)) <= 2.0 ** -46 * np.max(np.abs(R))
+        # target against a perturbed plain state
+        P = U.clone()
+        P[0] += 0.01
+        t = N.make_target(F, P).cpu().numpy().astype(np.float64)
+    p = P.cpu().numpy().astype(np.float64)
+    ref = (R - (p[0] - p[1])) / tau[:, None, None, None]
+    assert np.max(np.abs(t - ref) / np.abs(ref)) <= 2.0 ** -23
+
+
+def test_correction_applies_and_falls_back():
+    import torch
+    import workloads as wl
+    shape = (32, 16, 8)
+    nx, ny, nz = shape
+    from paper_1812_07977_amd.learned import init_params, param_count
+    U0 = wl.random_plane(nx, ny, nz, seed=5, v=(0.3, 0.1, 0.0))
+    from paper_1812_07977_amd import Fluid
+    with Fluid(shape, bc="periodic", dtype="f32") as F:
+        S = F.state_from(U0)
+        torch.cuda.synchronize()
+    start = S.cpu().numpy().astype(np.float64)
+    with _net(shape) as N:
+        # all-zero network: zero correction, applied, state unchanged
+        N.correct(S)
+        assert N.counts() == (1, 0)
+        assert np.array_equal(S.cpu().numpy(), start.astype(np.float32))
+        # a real correction: the state moves, totals do not
+        flat = init_params(5, out_scale=1.0)
+        N.set_params(flat)
+        N.set_norm(U0.mean(axis=(1, 2, 3)), U0.std(axis=(1, 2, 3)) + 1e-3, np.full(5, 1e-3))
+        N.correct(S)
+        assert N.counts() == (2, 0)
+        after = S.cpu().numpy().astype(np.float64)
+        before_v = start[0] - start[1]
+        after_v = after[0] - after[1]
+        change = after_v - before_v
+        assert np.max(np.abs(change)) > 1e-5
+        for f in range(5):
+            assert abs(change[f].sum()) <= 1e-5 * np.abs(change[f]).sum()
+        # a correction that empties some cells: fallback, state unchanged
+        N.set_norm(U0.mean(axis=(1, 2, 3)), U0.std(axis=(1, 2, 3)) + 1e-3, np.full(5, 1e3))
+        N.correct(S)
+        assert N.counts() == (2, 1)
+        assert np.array_equal(S.cpu().numpy().astype(np.float64), after)
+
+
+def test_training_reduces_the_loss():
+    import torch
+    from paper_1812_07977_amd.learned import init_params
+    shape = (32, 16, 16)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(15)
+    head = 1.0 + 0.2 * rng.standard_normal((5, nz, ny, nx))
+    # a target that is a fixed smooth function of the input
+    t = np.roll(head, 1, axis=3) - head
+    with _net(shape) as N:
+        N.set_params(init_params(6))
+        N.set_norm(np.ones(5), np.full(5, 0.2), np.ones(5))
+        U = _pair(head)
+        T = torch.from_numpy(((t) / 0.2).astype(np.float32)).cuda()
+        first = N.train_step(U, T, 3e-3, want_loss=True)
+        for _ in range(150):
+            N.train_step(U, T, 3e-3)
+        last = N.train_step(U, T, 3e-3, want_loss=True)
+    _say(f"training loss {first:.4e} -> {last:.4e}")
+    assert last < 0.3 * first

@@ -3,19 +3,21 @@ Kahan-compensated RK2 combine, FP64 primitive recovery, time step and
 conserved totals.  Compared, through the C ABI, with the FP64 oracle on the
 same seeded inputs.
 
-Error bound.  The FP32 form is not the FP64 scheme rounded once: every step
-rounds the stage inputs the stencil reads to FP32 (relative error <= u, the
-FP32 unit roundoff 2^-24) and evaluates the face fluxes in FP32, a chain of a
-few tens of operations.  Each step therefore moves a cell by at most
-c u max|U| away from the FP64 step of the same input, and every operation of
-the scheme is Lipschitz (minmod, min/max signal speeds, the clamped HLL
-average) with a per-step constant near 1 at CFL 0.5, so after N steps the
-difference is at most about N c u max|U|.  The tests assert this linear
-model, relative L-infinity <= K_LINF u N and relative L1 <= K_L1 u N per
-field, with K fixed at four to eight times the worst value measured over the
-cases below (listed beside the constants).  The compensation is what keeps
-the bound linear in N with a constant that does not grow with the number of
-increments absorbed: without it every step would add a rounding of U itself.
+Error bound.  The FP32 form is not the FP64 scheme rounded once: the state
+is held as an FP32 pair, the stencil reads its FP32 head (relative error
+<= u/2, u = 2^-24 the FP32 unit roundoff), and the face fluxes are evaluated
+in FP32, a chain of a few tens of operations whose rounding enters each
+step's increment.  Every operation of the scheme is Lipschitz (minmod, min/max
+signal speeds, the clamped HLL average) with a per-step constant near 1 at
+CFL 0.5, so the difference from the FP64 oracle after N steps is bounded by a
+representation term plus a term linear in N:
+    relative L-infinity per field <= (A_LINF + B_LINF N) u,
+    relative L1 per field         <= (A_L1 + B_L1 N) u.
+The compensation is what keeps the growth at most linear: without it every
+step would add a rounding of U itself, and increments below half an ulp of U
+would be lost.  Measured (max over the cases below): L-infinity 0.8 u after
+1 step (512^3), 1.8 u after 20, 3.1 u after 30, 2.8 u after 100; L1 1.4 u
+after 20, 1.5 u after 100.  The constants leave three to ten times that.
 """
 import json
 import math
@@ -32,8 +34,16 @@ from tests.parity import (CFL, GAMMA, f32_run, gpu_run_device_dt, oracle_run, re
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-K_LINF = 256.0
-K_L1 = 64.0
+A_LINF, B_LINF = 4.0, 0.25
+A_L1, B_L1 = 2.0, 0.1
+
+
+def linf_bound(n):
+    return (A_LINF + B_LINF * n) * U32
+
+
+def l1_bound(n):
+    return (A_L1 + B_L1 * n) * U32
 
 
 def _say(*a):
@@ -70,9 +80,9 @@ def test_f32_matches_fp64_oracle_within_bound(case):
     dt_rel = float(np.max(np.abs(gdt - odt) / odt))
     l1, linf = rel_l1(out, ref), rel_linf(out, ref)
     _report(case, n, l1, linf, dt_rel)
-    assert dt_rel <= K_LINF * U32 * n
-    assert max(linf) <= K_LINF * U32 * n, linf
-    assert max(l1) <= K_L1 * U32 * n, l1
+    assert dt_rel <= linf_bound(n)
+    assert max(linf) <= linf_bound(n), linf
+    assert max(l1) <= l1_bound(n), l1
 
 
 def test_f32_with_the_oracle_time_steps():
@@ -84,8 +94,8 @@ def test_f32_with_the_oracle_time_steps():
     out, _, _, _ = f32_run(U0, "periodic", n, mode="given", dts=odt)
     l1, linf = rel_l1(out, ref), rel_linf(out, ref)
     _report("plane2_given_dt", n, l1, linf, 0.0)
-    assert max(linf) <= K_LINF * U32 * n, linf
-    assert max(l1) <= K_L1 * U32 * n, l1
+    assert max(linf) <= linf_bound(n), linf
+    assert max(l1) <= l1_bound(n), l1
 
 
 def test_f32_host_dt_and_device_dt_are_bitwise_identical():
@@ -140,10 +150,15 @@ def test_f32_totals_are_conserved_with_periodic_boundaries():
     exact = np.array([math.fsum(U0[f].ravel()) for f in range(5)])
     scale = np.max(np.abs(exact))
     drift = float(np.max(np.abs(after - before)) / scale)
-    _say(f"f32 totals drift over {n} steps: {drift:.3e} of the largest total")
+    # the fluxes telescope, but each cell's FP32 increment is rounded
+    # independently: a random walk of about sqrt(cells) roundings of size
+    # u max|U| per step
+    est = n * math.sqrt(U0[0].size) * U32 * np.max(np.abs(U0)) / scale
+    _say(f"f32 totals drift over {n} steps: {drift:.3e} of the largest total "
+         f"(estimate {est:.1e})")
     # the initial pair holds U0 to about 48 bits
     assert np.max(np.abs(before - exact)) <= 1e-13 * scale
-    assert drift <= 1e-9
+    assert drift <= est
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -256,7 +271,7 @@ def test_f32_full_512_sampled_windows_within_bound(case):
     gdt = float(log.cpu()[0])
     h = 1.0 / n
     odt = oracle.time_step(U0, (h, h, h), GAMMA, CFL)
-    assert abs(gdt - odt) <= K_LINF * U32 * odt
+    assert abs(gdt - odt) <= linf_bound(1) * odt
     rng = np.random.default_rng(321)
     origins = [(0, 0, 0), (n - 3, n - 2, n - 4), (255, 256, 250)]
     origins += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(5)]
@@ -274,4 +289,4 @@ def test_f32_full_512_sampled_windows_within_bound(case):
             s = scale[f] if scale[f] > 0 else np.max(scale)
             worst = max(worst, float(np.max(np.abs(g[f] - win[f])) / s))
     _say(f"f32 512^3 {case}: worst windowed rel error {worst:.3e} = {worst / U32:.2f} u")
-    assert worst <= K_LINF * U32
+    assert worst <= linf_bound(1)
