@@ -64,6 +64,22 @@ int gs_cnn_get_params(gs_cnn* h, float* host_params);
  * corrections, 5 host doubles each, one per conserved field. */
 int gs_cnn_set_norm(gs_cnn* h, const double* mu, const double* sigma, const double* tau);
 
+/*
+ * Input features and correction scales.  mode 0 (default): the inputs are
+ * the conserved fields and delta_f = tau_f (y_f - mean(y_f)), as above.
+ * mode 1 (scale-aware): the inputs are (log rho, v_x, v_y, v_z, log p) of
+ * the cell (FP64 primitive recovery, then normalised by mu and sigma), and
+ * delta_f = tau_f (S_f y_f - mean(S_f y_f)) with the cell's local scales
+ * S = (rho, rho c, rho c, rho c, E), c the sound speed; training targets are
+ * divided by tau_f S_f accordingly.  Under rho, p -> lambda rho, lambda p the
+ * inputs only shift and the corrections scale with the state, so one network
+ * serves density and pressure ratios far from its training data.
+ * clip > 0 clamps each normalised output y_f to [-clip, clip] before it is
+ * applied (a per-cell trust region against outputs far outside the
+ * training distribution); 0 applies y as it is.  Training is unaffected.
+ */
+int gs_cnn_set_features(gs_cnn* h, int mode, double clip);
+
 /* Network output y (device [5][nz][ny][nx] floats) for the head of U. */
 int gs_cnn_forward(gs_cnn* h, const void* U, float* y);
 
@@ -75,8 +91,8 @@ int gs_cnn_restrict(gs_cnn* h, const double* fine, void* U);
 
 /*
  * Training target for the plain-step state U: target_f = (R(fine)_f -
- * (head - compensation)_f) / tau_f, device [5][nz][ny][nx] floats, computed
- * in FP64.
+ * (head - compensation)_f) / tau_f (mode 1: / (tau_f S_f)), device
+ * [5][nz][ny][nx] floats, computed in FP64.
  */
 int gs_cnn_make_target(gs_cnn* h, const double* fine, const void* U, float* target);
 

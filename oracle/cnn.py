@@ -144,3 +144,24 @@ def bf16_round(x):
     lsb = (u >> 16) & 1
     u = (u + 0x7FFF + lsb) >> 16 << 16
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def features(U, gamma):
+    """Scale-aware network inputs of a conserved state U (5, ...): log rho,
+    the velocity components and log p (the Euler equations are invariant
+    under rho, p -> lambda rho, lambda p, and log turns that into a shift)."""
+    rho = U[0]
+    v = U[1:4] / rho
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * np.sum(v * v, axis=0))
+    return np.stack([np.log(rho), v[0], v[1], v[2], np.log(p)])
+
+
+def scales(U, gamma):
+    """Local scales of the corrections of each conserved field: rho for the
+    density, rho c for the three momenta (c the sound speed), E for the
+    energy."""
+    rho = U[0]
+    v = U[1:4] / rho
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * np.sum(v * v, axis=0))
+    rc = rho * np.sqrt(gamma * p / rho)
+    return np.stack([rho, rc, rc, rc, U[4]])

@@ -51,6 +51,7 @@ SIGNATURES = [
     ("gs_cnn_set_params", _I, [_VP, _VP]),
     ("gs_cnn_get_params", _I, [_VP, _VP]),
     ("gs_cnn_set_norm", _I, [_VP, _PD, _PD, _PD]),
+    ("gs_cnn_set_features", _I, [_VP, _I, _D]),
     ("gs_cnn_forward", _I, [_VP, _VP, _VP]),
     ("gs_cnn_restrict", _I, [_VP, _VP, _VP]),
     ("gs_cnn_make_target", _I, [_VP, _VP, _VP, _VP]),

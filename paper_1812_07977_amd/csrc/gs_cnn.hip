@@ -349,20 +349,66 @@ __global__ void bias_final_kernel(const float* __restrict__ part, int C, float* 
 // input packing, targets, loss, optimizer
 // ---------------------------------------------------------------------------
 
+// Inputs and correction scales.  mode 0: inputs are the conserved fields,
+// corrections are tau (y - mean y).  mode 1 (scale-aware): inputs are
+// (log rho, v_x, v_y, v_z, log p) and the correction of field f is
+// tau_f (S_f y_f - mean(S_f y_f)) with local scales S = (rho, rho c, rho c,
+// rho c, E) of the cell; both normalised per input by mu, sigma.
 struct Norm {
     float mu[NF], inv_sigma[NF];
     double tau[NF], inv_tau[NF];
+    double gamma;
+    double clip;  // > 0: the applied output is clamped to [-clip, clip]
+    int mode;
 };
 
-// head of an FP32 pair -> CL BF16 [v][8] of (U - mu) / sigma, channels 5..7 = 0
+// primitives of a cell in FP64 (no positivity guard: callers clamp logs
+// and square roots)
+__device__ __forceinline__ void cell_prims(const double u[NF], double gamma, double& rho,
+                                           double v[3], double& p)
+{
+    rho = u[0];
+    const double ir = 1.0 / rho;
+    v[0] = u[1] * ir;
+    v[1] = u[2] * ir;
+    v[2] = u[3] * ir;
+    p = (gamma - 1.0) * (u[4] - 0.5 * ((u[1] * v[0] + u[2] * v[1]) + u[3] * v[2]));
+}
+
+// local correction scales S of a cell (mode 1), from its FP64 values
+__device__ __forceinline__ void cell_scales(const double u[NF], double gamma, double S[NF])
+{
+    double rho, v[3], p;
+    cell_prims(u, gamma, rho, v, p);
+    const double rc = sqrt(fmax(gamma * p * rho, 1e-300));
+    S[0] = rho;
+    S[1] = S[2] = S[3] = rc;
+    S[4] = u[4];
+}
+
+// head of an FP32 pair -> CL BF16 [v][8] of (feature - mu) / sigma,
+// channels 5..7 = 0
 __global__ void pack_input_kernel(const float* __restrict__ U, long long ncell, Norm nm,
                                   u16* __restrict__ X)
 {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < ncell;
          v += (long long)gridDim.x * blockDim.x) {
+        float feat[NF];
+        if (nm.mode == 1) {
+            double u[NF], rho, vel[3], p;
+            for (int f = 0; f < NF; ++f) u[f] = (double)U[f * ncell + v];
+            cell_prims(u, nm.gamma, rho, vel, p);
+            feat[0] = (float)log(fmax(rho, 1e-300));
+            feat[1] = (float)vel[0];
+            feat[2] = (float)vel[1];
+            feat[3] = (float)vel[2];
+            feat[4] = (float)log(fmax(p, 1e-300));
+        } else {
+            for (int f = 0; f < NF; ++f) feat[f] = U[f * ncell + v];
+        }
         u16 x[8];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) x[f] = f2bf((U[f * ncell + v] - nm.mu[f]) * nm.inv_sigma[f]);
+        for (int f = 0; f < NF; ++f) x[f] = f2bf((feat[f] - nm.mu[f]) * nm.inv_sigma[f]);
         x[5] = x[6] = x[7] = 0;
         u32x4 w;
         w[0] = x[0] | ((unsigned)x[1] << 16);
@@ -402,8 +448,12 @@ __global__ void restrict_kernel(const double* __restrict__ fine, int nx, int ny,
                 U[f * ncell + v] = head;
                 U[(NF + f) * ncell + v] = (float)((double)head - r);
             } else {
-                const double u = (double)U[f * ncell + v] - (double)U[(NF + f) * ncell + v];
-                target[f * ncell + v] = (float)((r - u) * nm.inv_tau[f]);
+                double u[NF], S[NF];
+                for (int g = 0; g < NF; ++g)
+                    u[g] = (double)U[g * ncell + v] - (double)U[(NF + g) * ncell + v];
+                if (nm.mode == 1) cell_scales(u, nm.gamma, S);
+                const double scale = nm.mode == 1 ? nm.tau[f] * S[f] : nm.tau[f];
+                target[f * ncell + v] = (float)((r - u[f]) / scale);
             }
         }
     }
@@ -484,15 +534,38 @@ __device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
     s = t;
 }
 
+// the per-field quantity whose mean the correction removes: y (mode 0) or
+// S y (mode 1), S from the head of U
+__device__ __forceinline__ void scaled_output(const float* __restrict__ U, const float* __restrict__ y,
+                                              long long ncell, long long v, const Norm& nm,
+                                              double out[NF])
+{
+    double S[NF] = {1.0, 1.0, 1.0, 1.0, 1.0};
+    if (nm.mode == 1) {
+        double u[NF];
+        for (int f = 0; f < NF; ++f) u[f] = (double)U[f * ncell + v];
+        cell_scales(u, nm.gamma, S);
+    }
+    for (int f = 0; f < NF; ++f) {
+        double yy = (double)y[f * ncell + v];
+        if (nm.clip > 0.0) yy = fmin(fmax(yy, -nm.clip), nm.clip);
+        out[f] = S[f] * yy;
+    }
+}
+
 __global__ void __launch_bounds__(THREADS)
-mean_partial_kernel(const float* __restrict__ y, long long ncell, double* __restrict__ partial)
+mean_partial_kernel(const float* __restrict__ U, const float* __restrict__ y, long long ncell,
+                    Norm nm, double* __restrict__ partial)
 {
     __shared__ double rs[NF][THREADS / 64], rc[NF][THREADS / 64];
     double s[NF], c[NF];
     for (int f = 0; f < NF; ++f) s[f] = c[f] = 0.0;
     for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
-         v += (long long)gridDim.x * THREADS)
-        for (int f = 0; f < NF; ++f) two_sum_add(s[f], c[f], (double)y[f * ncell + v]);
+         v += (long long)gridDim.x * THREADS) {
+        double q[NF];
+        scaled_output(U, y, ncell, v, nm, q);
+        for (int f = 0; f < NF; ++f) two_sum_add(s[f], c[f], q[f]);
+    }
     for (int f = 0; f < NF; ++f) {
         for (int off = 32; off > 0; off >>= 1) {
             double s2 = __shfl_xor(s[f], off), c2 = __shfl_xor(c[f], off);
@@ -544,10 +617,11 @@ apply_kernel(const float* __restrict__ U, const float* __restrict__ y, long long
     bool bad = false;
     for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
          v += (long long)gridDim.x * THREADS) {
-        double u[NF], w[NF];
+        double u[NF], w[NF], q[NF];
+        scaled_output(U, y, ncell, v, nm, q);
         for (int f = 0; f < NF; ++f) {
             const float head = U[f * ncell + v], comp = U[(NF + f) * ncell + v];
-            const float d = (float)(nm.tau[f] * ((double)y[f * ncell + v] - csr->mean[f]));
+            const float d = (float)(nm.tau[f] * (q[f] - csr->mean[f]));
             const float yy = d - comp;
             const float s = head + yy;
             const float c2 = (s - head) - yy;
@@ -849,6 +923,9 @@ int gs_cnn_create(int nx, int ny, int nz, int bc, double gamma, void* stream, gs
     h->stream = (hipStream_t)stream;
     h->ncell = (long long)nx * ny * nz;
     h->step = 0;
+    h->norm.gamma = gamma;
+    h->norm.clip = 0.0;
+    h->norm.mode = 0;
     for (int f = 0; f < NF; ++f) {
         h->norm.mu[f] = 0.0f;
         h->norm.inv_sigma[f] = 1.0f;
@@ -949,6 +1026,16 @@ int gs_cnn_set_norm(gs_cnn* h, const double* mu, const double* sigma, const doub
     return GS_OK;
 }
 
+int gs_cnn_set_features(gs_cnn* h, int mode, double clip)
+{
+    if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (mode != 0 && mode != 1) return cfail(h, GS_ERR_ARG, "mode must be 0 or 1");
+    if (!std::isfinite(clip) || clip < 0.0) return cfail(h, GS_ERR_ARG, "clip must be finite and >= 0");
+    h->norm.mode = mode;
+    h->norm.clip = clip;
+    return GS_OK;
+}
+
 int gs_cnn_forward(gs_cnn* h, const void* U, float* y)
 {
     if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
@@ -1032,8 +1119,8 @@ int gs_cnn_correct(gs_cnn* h, void* U)
     k.inv_gm1 = 1.0 / (h->gamma - 1.0);
     for (int d = 0; d < 3; ++d) k.inv_h[d] = 1.0;
     k.cfl = 1.0;
-    hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, n,
-                       h->red);
+    hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream,
+                       (const float*)U, h->y, n, h->norm, h->red);
     hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, h->stream, h->red, RED_BLOCKS, n, h->cs);
     hipLaunchKernelGGL(apply_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
                        h->y, n, h->norm, k, h->cs, h->cand, h->red, h->cs);

@@ -78,7 +78,9 @@ def _dyadic_params(rng):
 
 
 @pytest.mark.parametrize("shape,bc", [((32, 16, 8), "periodic"), ((20, 12, 6), "outflow"),
-                                      ((16, 16, 16), "periodic")])
+                                      ((16, 16, 16), "periodic"),
+                                      # 16 tiles and 160 planes: workgroups march 2 planes
+                                      ((64, 64, 160), "periodic")])
 def test_forward_is_bit_exact_on_exactly_representable_data(shape, bc):
     nx, ny, nz = shape
     _say(f"case: cnn forward dyadic {shape} {bc}")
@@ -280,3 +282,82 @@ def test_training_reduces_the_loss():
         last = N.train_step(U, T, 3e-3, want_loss=True)
     _say(f"training loss {first:.4e} -> {last:.4e}")
     assert last < 0.3 * first
+
+
+def test_scale_aware_inputs_match_the_oracle():
+    # mode 1: inputs (log rho, v, log p) from FP64 primitive recovery of the
+    # head, normalised in FP32 and rounded to BF16
+    import workloads as wl
+    shape = (32, 16, 12)
+    nx, ny, nz = shape
+    from paper_1812_07977_amd.learned import init_params
+    U0 = wl.random_plane(nx, ny, nz, seed=3, v=(0.4, -0.3, 0.2))
+    head = U0.astype(np.float32).astype(np.float64)
+    flat = init_params(7, out_scale=1.0)
+    feats = ocnn.features(head, 1.4)
+    mu = feats.mean(axis=(1, 2, 3))
+    sigma = feats.std(axis=(1, 2, 3)) + 0.1
+    with _net(shape) as N:
+        N.set_params(flat)
+        N.set_features(1)
+        N.set_norm(mu, sigma, np.ones(5))
+        y = N.forward(_pair(head)).cpu().numpy().astype(np.float64)
+    f32 = feats.astype(np.float32)
+    x = ocnn.bf16_round(((f32 - mu.astype(np.float32)[:, None, None, None])
+                         * (1.0 / sigma).astype(np.float32)[:, None, None, None]).astype(np.float64))
+    params = _params_from_flat(flat)
+    ref, (a1, h1, a2, h2) = _oracle_forward_bf16(x, params, ocnn.PERIODIC)
+    r = ocnn.bf16_round
+    w1, w2, w3 = r(params[0][0]), r(params[1][0]), r(params[2][0])
+    z32, z5 = np.zeros(HIDDEN_CH), np.zeros(5)
+    # as in the random-weight test, plus one BF16 unit of the inputs (the
+    # device and numpy logarithms may round a feature differently)
+    e0 = 2.0 ** -8 * np.abs(x)
+    e1 = 2.0 ** -8 * np.abs(h1) + ocnn.conv3(e0, np.abs(w1), z32, ocnn.PERIODIC)
+    e2 = 2.0 ** -8 * np.abs(h2) + ocnn.conv3(e1, np.abs(w2), z32, ocnn.PERIODIC)
+    absum = ocnn.conv3(np.abs(h2), np.abs(w3), np.abs(params[2][1]), ocnn.PERIODIC)
+    bound = ocnn.conv3(e2, np.abs(w3), z5, ocnn.PERIODIC) + 1e-5 * absum
+    err = np.abs(y - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    assert np.median(err / absum) < 1e-3
+
+
+def test_scale_aware_targets_and_clipped_correction():
+    import torch
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    from paper_1812_07977_amd.learned import init_params
+    shape = (16, 12, 10)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(16)
+    fine = wl.random_plane(2 * nx, 2 * ny, 2 * nz, seed=2, v=(0.3, 0.2, -0.1))
+    tau = np.array([0.01, 0.02, 0.02, 0.02, 0.03])
+    with _net(shape) as N:
+        N.set_features(1)
+        N.set_norm(np.zeros(5), np.ones(5), tau)
+        F = torch.from_numpy(fine).cuda()
+        U = N.restrict(F)
+        U[0] *= torch.from_numpy((1.0 + 0.01 * rng.standard_normal((5, nz, ny, nx))).astype(np.float32)).cuda()
+        t = N.make_target(F, U).cpu().numpy().astype(np.float64)
+        p = U.cpu().numpy().astype(np.float64)
+        u = p[0] - p[1]
+        S = ocnn.scales(u, 1.4)
+        ref = (ocnn.restrict2(fine) - u) / (tau[:, None, None, None] * S)
+        assert np.max(np.abs(t - ref) / np.maximum(np.abs(ref), 1e-30)) <= 2.0 ** -20
+        # correction relative to local scales, clipped at 0.5: every cell
+        # moves by at most tau S 0.5 (plus the mean removal), totals stay
+        N.set_params(init_params(8, out_scale=1.0))
+        N.set_norm(np.array([0.0, 0.0, 0.0, 0.0, 0.0]), np.ones(5), tau)
+        N.set_features(1, 0.5)
+        before = U.cpu().numpy().astype(np.float64)
+        N.correct(U)
+        assert N.counts() == (1, 0)
+        after = U.cpu().numpy().astype(np.float64)
+    change = (after[0] - after[1]) - (before[0] - before[1])
+    Sb = ocnn.scales(before[0].astype(np.float64), 1.4)
+    lim = tau[:, None, None, None] * Sb * 0.5
+    for f in range(5):
+        mean_shift = tau[f] * np.max(Sb[f]) * 0.5
+        assert np.all(np.abs(change[f]) <= lim[f] + mean_shift + 1e-6 * np.abs(before[0][f])), f
+        assert abs(change[f].sum()) <= 1e-5 * np.abs(change[f]).sum()
+    assert np.max(np.abs(change)) > 0

@@ -136,3 +136,27 @@ def test_bf16_rounding_matches_torch():
                         [1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9, -0.0, 65504.0]])
     ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(cnn.bf16_round(x), ref)
+
+
+def test_features_and_scales_of_a_hand_computed_state():
+    # rho = 2, v = (1, -2, 0.5), p = 3, gamma = 1.4: E = 3 / 0.4 + 0.5 * 2 * 5.25
+    gamma = 1.4
+    U = np.array([2.0, 2.0, -4.0, 1.0, 7.5 + 5.25]).reshape(5, 1, 1, 1)
+    f = cnn.features(U, gamma)[:, 0, 0, 0]
+    np.testing.assert_allclose(f, [np.log(2.0), 1.0, -2.0, 0.5, np.log(3.0)], rtol=1e-14)
+    s = cnn.scales(U, gamma)[:, 0, 0, 0]
+    c = np.sqrt(1.4 * 3.0 / 2.0)
+    np.testing.assert_allclose(s, [2.0, 2.0 * c, 2.0 * c, 2.0 * c, 12.75], rtol=1e-14)
+
+
+def test_features_shift_under_mass_scaling():
+    # rho, m, E -> lambda (rho, m, E) leaves v unchanged and shifts both logs
+    rng = np.random.default_rng(8)
+    rho = 0.5 + rng.random((2, 3, 4))
+    v = rng.standard_normal((3, 2, 3, 4))
+    p = 0.5 + rng.random((2, 3, 4))
+    U = np.concatenate([rho[None], rho * v, (p / 0.4 + 0.5 * rho * np.sum(v * v, 0))[None]])
+    f1, f2 = cnn.features(U, 1.4), cnn.features(7.0 * U, 1.4)
+    np.testing.assert_allclose(f2[1:4], f1[1:4], rtol=1e-13)
+    np.testing.assert_allclose(f2[[0, 4]] - f1[[0, 4]], np.log(7.0), rtol=1e-12)
+    np.testing.assert_allclose(cnn.scales(7.0 * U, 1.4), 7.0 * cnn.scales(U, 1.4), rtol=1e-13)
