@@ -188,6 +188,113 @@ def f32_error(U0, n, dts, U64):
     return l1, linf
 
 
+def learned_form(n=128, iters=6000, eval_steps=200, stride=5, eval_seed=99):
+    """The learned-correction form on the coarse/fine pair n^3 / (2n)^3
+    (periodic unit cubes): train the network on fine FP64 runs restricted
+    2:1 (seeded random-plane Riemann problems and sine waves), then time, to
+    the same end time on a held-out Riemann problem, the fine FP64 solve, the
+    plain coarse FP32 solve and the corrected coarse FP32 solve, and measure
+    both coarse solves' L1 errors against the restricted fine solve."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    from paper_1812_07977_amd import learned as L
+    f = 2 * n
+    t0 = time.perf_counter()
+    net = L.CorrectionNet((n, n, n))
+    net.set_params(L.init_params(0))
+    net.set_norm(np.zeros(5), np.ones(5), np.ones(5))
+
+    def sine(seed):
+        rng = np.random.default_rng(seed)
+        k = tuple(int(v) for v in rng.integers(-2, 3, 3))
+        k = (1, 1, 1) if k == (0, 0, 0) else k
+        v = tuple(float(x) for x in rng.uniform(-1, 1, 3))
+        return wl.sine_wave(f, f, f, k=k, v=v, amp=0.2)
+
+    states = [torch.from_numpy(wl.random_plane(f, f, f, seed=s)).cuda() for s in range(6)]
+    states += [torch.from_numpy(sine(s)).cuda() for s in (100, 101)]
+    # training states spread over the whole evaluated time window
+    inputs, raw = L.generate_samples(net, states, eval_steps, stride=stride)
+    mu, sigma, tau = L.normalisation(inputs, raw)
+    net.set_norm(mu, sigma, tau)
+    tt = torch.tensor(tau, dtype=torch.float32, device="cuda")[:, None, None, None]
+    targets = [r / tt for r in raw]
+    del raw
+    L.train(net, inputs, targets, iters, lr=3e-4)
+    del inputs, targets
+    alpha, blend_errs = L.fit_blend(net, states[:2], eval_steps // 2,
+                                    alphas=(0.0, 0.25, 0.5, 0.75, 1.0))
+    del states
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    U0 = torch.from_numpy(wl.random_plane(f, f, f, seed=eval_seed)).cuda()
+    Cp = Fluid((n,) * 3, bc="periodic", dtype="f32")
+    # the time grid: the plain coarse run's own CFL steps
+    plain = net.restrict(U0)
+    dts = []
+    for _ in range(eval_steps):
+        dt = Cp.dt(plain)
+        dts.append(dt)
+        Cp.step(plain, dt)
+    T = float(sum(dts))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev0.record()
+        fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    plain = net.restrict(U0)
+    ms_plain = timed(lambda: [Cp.step(plain, dt) for dt in dts])
+    corr = net.restrict(U0)
+    a0, f0 = net.counts()
+
+    def corrected():
+        for dt in dts:
+            Cp.step(corr, dt)
+            if alpha > 0:
+                net.correct(corr)
+    ms_corr = timed(corrected)
+    a1, f1 = net.counts()
+    # the fine FP64 solve to the same time: count its steps once, then time
+    Ff = Fluid((f,) * 3, bc="periodic", dtype="f64")
+    Uf = U0.clone()
+    log = torch.zeros(8 * eval_steps, dtype=torch.float64, device="cuda")
+    Ff.advance(Uf, 8 * eval_steps, T, log)
+    Ff.sync()
+    nfine = int((log > 0).sum())
+    Uf = U0.clone()
+    Ff.time = 0.0
+    ms_fine = timed(lambda: Ff.advance(Uf, nfine, T))
+    errs = L._errors(net, Uf, plain, corr)
+    Ff.close()
+    Cp.close()
+    net.close()
+    return {
+        "workload": f"held-out random-plane Riemann problem (seed {eval_seed}), {n}^3 coarse FP32 "
+                    f"+ network vs {f}^3 FP64, {eval_steps} coarse steps to t = {T:.5f}",
+        "value": n ** 3 * eval_steps / (ms_corr / 1e3), "unit": "coarse cell-updates/s",
+        "ms_corrected": round(ms_corr, 2), "ms_plain_coarse": round(ms_plain, 2),
+        "ms_fine_f64": round(ms_fine, 2), "fine_steps": nfine,
+        "speedup_vs_f64": round(ms_fine / ms_corr, 3),
+        "l1_rel_err_corrected": [round(x, 5) for x in errs["l1_corrected"]],
+        "l1_rel_err_plain_coarse": [round(x, 5) for x in errs["l1_plain"]],
+        "l1_fields": ["rho", "momentum (all components)", "E"],
+        "error_vs": f"the {f}^3 FP64 solve restricted 2:1 at the same time",
+        "corrections_applied": a1 - a0, "fallbacks": f1 - f0, "blend": alpha,
+        "blend_fit_l1": {str(k): round(v, 5) for k, v in blend_errs.items()},
+        "training": f"{iters} Adam steps on 8 trajectories x {eval_steps // stride} states "
+                    f"(every {stride}th of {eval_steps} steps; {f}^3 FP64 restricted), "
+                    f"{t_train:.1f} s incl. data",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +378,9 @@ def main():
                         "steps (same dt sequence)",
             "roofline": roof32, "alu": alu32}}
     del U64
+    if not args.no_forms:
+        print("bench: learned-correction form (training, then timing)", file=sys.stderr, flush=True)
+        line["forms"]["learned"] = learned_form()
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -219,29 +219,31 @@ def _solvers(n, gamma, cfl):
     return fine, coarse
 
 
-def generate_samples(net, fine_states, steps, gamma=1.4, cfl=0.5):
+def generate_samples(net, fine_states, steps, gamma=1.4, cfl=0.5, stride=1):
     """Training pairs from fine FP64 runs.  For each initial fine state (a
     float64 GPU tensor (5, 2n, 2n, 2n)) and each of `steps` coarse steps: the
     coarse state R(fine) takes one plain FP32 step of the coarse CFL time step
     dt; the fine solve advances to the same time; the target is R(fine) minus
-    the plain-step state.  Returns (inputs, raw targets): lists of GPU
-    tensors, the pairs after the plain step and the unscaled corrections.
-    The net's normalisation must have tau = 1 while this runs."""
+    the plain-step state.  Every stride-th step is kept.  Returns (inputs, raw
+    targets): lists of GPU tensors, the pairs after the plain step and the
+    unscaled corrections.  The net's normalisation must have tau = 1 while
+    this runs."""
     n = net.shape[0]
     inputs, targets = [], []
     for U0 in fine_states:
         F, C = _solvers(n, gamma, cfl)
         Uf = U0.clone()
         t = 0.0
-        for _ in range(steps):
+        for k in range(steps):
             Uc = net.restrict(Uf)
             dt = C.dt(Uc)
             C.step(Uc, dt)
             F.time = t
             F.advance(Uf, 8, t + dt)
             t += dt
-            inputs.append(Uc)
-            targets.append(net.make_target(Uf, Uc))
+            if k % stride == stride - 1:
+                inputs.append(Uc)
+                targets.append(net.make_target(Uf, Uc))
         F.close()
         C.close()
     return inputs, targets
@@ -337,16 +339,23 @@ def train(net, inputs, targets, iters, lr=1e-3, seed=0, log_every=0, augment=Tru
 def fit_blend(net, fine_states, steps, alphas=(0.25, 0.5, 0.75, 1.0), gamma=1.4, cfl=0.5):
     """The factor alpha that scales the applied correction: the one with the
     smallest mean L1 error after `steps` corrected steps over the given
-    (training) trajectories.  Sets the net's tau to alpha tau and returns
+    (training) trajectories; alpha = 0 (no correction: the plain coarse
+    solve) may be listed.  Sets the net's tau to alpha tau (alpha = 0 keeps
+    tau and returns 0: the caller then skips the correction) and returns
     (alpha, {alpha: error})."""
     mu, sigma, tau = net._norm
     errs = {}
     for a in alphas:
+        if a == 0:
+            e = [np.mean(evaluate(net, U, steps, gamma, cfl, with_net=False)["l1_plain"])
+                 for U in fine_states]
+            errs[a] = float(np.mean(e))
+            continue
         net.set_norm(mu, sigma, a * tau)
         e = [np.mean(evaluate(net, U, steps, gamma, cfl)["l1_corrected"]) for U in fine_states]
         errs[a] = float(np.mean(e))
     best = min(errs, key=errs.get)
-    net.set_norm(mu, sigma, best * tau)
+    net.set_norm(mu, sigma, (best if best > 0 else 1.0) * tau)
     return best, errs
 
 
