@@ -3,7 +3,7 @@ and the compensated FP32 form beside it.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--size 512]
                     [--case sine|plane] [--no-cpu-baseline] [--no-forms]
-                    [--copy-probe MIB]
+                    [--forms f32,learned] [--learned-iters N] [--copy-probe MIB]
 
 A step is one RK2 step of the whole hot path on the periodic cube: the two
 fused substep kernels, with the CFL max-reduction fused into the second one
@@ -306,6 +306,10 @@ def main():
     ap.add_argument("--chunk-z", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the FP64 form only")
+    ap.add_argument("--forms", default="f32,learned",
+                    help="comma list of the forms to run beside FP64: f32, learned")
+    ap.add_argument("--learned-iters", type=int, default=6000,
+                    help="Adam steps of the learned form's training")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -358,14 +362,16 @@ def main():
                    "(Summit, 256^3 per rank, incl. host transfers)",
     }
 
-    if not args.no_forms:
+    forms = set() if args.no_forms else {f for f in args.forms.split(",") if f}
+    line["forms"] = {}
+    if "f32" in forms:
         print("bench: FP32 form", file=sys.stderr, flush=True)
         r32, _, _ = timed_run(U0, n, "f32", args.steps, args.warmup, args.tile_y, args.chunk_z)
         ms32 = r32["total_ms"] / args.steps
         roof32, alu32 = roofline("f32", n, args.case, r32["per_kernel"])
         print("bench: FP32 form error against FP64", file=sys.stderr, flush=True)
         l1, linf = f32_error(U0, n, dts64, U64)
-        line["forms"] = {"f32": {
+        line["forms"]["f32"] = {
             "value": cells * args.steps / (r32["total_ms"] / 1e3), "unit": "cell-updates/s",
             "ms_per_step": ms32, "speedup_vs_f64": round(ms_per_step / ms32, 3),
             "dtype": "f32 state and flux arithmetic; f64 primitive recovery, dt, totals",
@@ -376,11 +382,11 @@ def main():
             "l1_rel_err": l1, "linf_rel_err": linf,
             "error_vs": f"FP64 solution of the same input after the same {args.warmup + args.steps} "
                         "steps (same dt sequence)",
-            "roofline": roof32, "alu": alu32}}
+            "roofline": roof32, "alu": alu32}
     del U64
-    if not args.no_forms:
+    if "learned" in forms:
         print("bench: learned-correction form (training, then timing)", file=sys.stderr, flush=True)
-        line["forms"]["learned"] = learned_form()
+        line["forms"]["learned"] = learned_form(iters=args.learned_iters)
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

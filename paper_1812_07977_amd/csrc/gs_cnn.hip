@@ -589,13 +589,21 @@ mean_partial_kernel(const float* __restrict__ U, const float* __restrict__ y, lo
     }
 }
 
-__global__ void mean_final_kernel(const double* __restrict__ partial, int n, long long ncell,
-                                  CorrState* __restrict__ cs)
+// one wave per field: TwoSum over the block partials, lane-strided, then a
+// fixed shuffle tree
+__global__ void __launch_bounds__(64 * NF)
+mean_final_kernel(const double* __restrict__ partial, int n, long long ncell,
+                  CorrState* __restrict__ cs)
 {
-    if (threadIdx.x < NF) {
-        const int f = threadIdx.x;
-        double S = 0.0, C = 0.0;
-        for (int b = 0; b < n; ++b) two_sum_add(S, C, partial[b * NF + f]);
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double S = 0.0, C = 0.0;
+    for (int b = lane; b < n; b += 64) two_sum_add(S, C, partial[b * NF + f]);
+    for (int off = 32; off > 0; off >>= 1) {
+        double s2 = __shfl_xor(S, off), c2 = __shfl_xor(C, off);
+        two_sum_add(S, C, s2);
+        C += c2;
+    }
+    if (lane == 0) {
         cs->mean[f] = (S + C) / (double)ncell;
         cs->moved[f] = 0.0;
         cs->mag[f] = 0.0;
@@ -649,26 +657,37 @@ apply_kernel(const float* __restrict__ U, const float* __restrict__ y, long long
 }
 
 // decision: accept unless non-physical, or some |total change| exceeds
-// 1e-5 of the change's magnitude plus 1e-30 (also false for NaN)
-__global__ void decide_kernel(const double* __restrict__ partial, int n, CorrState* __restrict__ cs)
+// 1e-5 of the change's magnitude plus 1e-30 (also false for NaN).  One wave
+// per field sums the block partials in a fixed order.
+__global__ void __launch_bounds__(64 * NF)
+decide_kernel(const double* __restrict__ partial, int n, CorrState* __restrict__ cs)
 {
-    if (threadIdx.x != 0) return;
-    bool ok = cs->bad == 0u;
-    for (int f = 0; f < NF; ++f) {
-        double moved = 0.0, mag = 0.0;
-        for (int b = 0; b < n; ++b) {
-            moved += partial[b * 2 * NF + 2 * f];
-            mag += partial[b * 2 * NF + 2 * f + 1];
-        }
+    __shared__ int okf[NF];
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double moved = 0.0, mag = 0.0;
+    for (int b = lane; b < n; b += 64) {
+        moved += partial[b * 2 * NF + 2 * f];
+        mag += partial[b * 2 * NF + 2 * f + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        moved += __shfl_xor(moved, off);
+        mag += __shfl_xor(mag, off);
+    }
+    if (lane == 0) {
         cs->moved[f] = moved;
         cs->mag[f] = mag;
-        ok = ok && (fabs(moved) <= 1e-5 * mag + 1e-30);
+        okf[f] = (fabs(moved) <= 1e-5 * mag + 1e-30) ? 1 : 0;
     }
-    cs->ok = ok ? 1 : 0;
-    if (ok)
-        cs->applied += 1;
-    else
-        cs->fallbacks += 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = cs->bad == 0u;
+        for (int g = 0; g < NF; ++g) ok = ok && okf[g];
+        cs->ok = ok ? 1 : 0;
+        if (ok)
+            cs->applied += 1;
+        else
+            cs->fallbacks += 1;
+    }
 }
 
 __global__ void commit_kernel(const float* __restrict__ cand, long long n, const CorrState* __restrict__ cs,
@@ -1121,10 +1140,11 @@ int gs_cnn_correct(gs_cnn* h, void* U)
     k.cfl = 1.0;
     hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream,
                        (const float*)U, h->y, n, h->norm, h->red);
-    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64), 0, h->stream, h->red, RED_BLOCKS, n, h->cs);
+    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, n,
+                       h->cs);
     hipLaunchKernelGGL(apply_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
                        h->y, n, h->norm, k, h->cs, h->cand, h->red, h->cs);
-    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, h->stream, h->red, RED_BLOCKS, h->cs);
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, h->cs);
     hipLaunchKernelGGL(commit_kernel, dim3(grid_for(n * 2 * NF)), dim3(THREADS), 0, h->stream, h->cand,
                        n * 2 * NF, h->cs, (float*)U);
     e = hipGetLastError();
