@@ -188,7 +188,7 @@ def f32_error(U0, n, dts, U64):
     return l1, linf
 
 
-def learned_form(n=128, iters=6000, eval_steps=200, stride=5, eval_seed=99):
+def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
     """The learned-correction form on the coarse/fine pair n^3 / (2n)^3
     (periodic unit cubes): train the network on fine FP64 runs restricted
     2:1 (seeded random-plane Riemann problems and sine waves), then time, to
@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="time the FP64 form only")
     ap.add_argument("--forms", default="f32,learned",
                     help="comma list of the forms to run beside FP64: f32, learned")
-    ap.add_argument("--learned-iters", type=int, default=6000,
+    ap.add_argument("--learned-iters", type=int, default=8000,
                     help="Adam steps of the learned form's training")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter scaling)")
