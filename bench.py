@@ -3,7 +3,7 @@ and the compensated FP32 form beside it.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--size 512]
                     [--case sine|plane] [--no-cpu-baseline] [--no-forms]
-                    [--forms f32,learned] [--learned-iters N] [--copy-probe MIB]
+                    [--forms f32,batch,learned] [--learned-iters N] [--copy-probe MIB]
 
 A step is one RK2 step of the whole hot path on the periodic cube: the two
 fused substep kernels, with the CFL max-reduction fused into the second one
@@ -295,6 +295,76 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
     }
 
 
+def batched_form(dtype, steps=20, count=64, seed=1):
+    """The batched form: count seeded random-plane Riemann problems with
+    meshes drawn from 32..160 per axis (periodic), each with its own device
+    time step, advanced as one autotuned batch (one captured graph replay per
+    step) and, from the same inputs, one problem at a time through the
+    single-problem path; whole-batch cell-updates/s of both."""
+    import torch
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    from paper_1812_07977_amd.batch import Batch
+    dims, probs = wl.random_batch(count, seed)
+    cells = sum(nx * ny * nz for nx, ny, nz in dims)
+    handles = [Fluid((nx, ny, nz), bc="periodic", dtype=dtype) for nx, ny, nz in dims]
+    init = [F.state_from(U0) for F, U0 in zip(handles, probs)]
+    del probs
+    states = [S.clone() for S in init]
+    B = Batch(dims, states, bc="periodic", dtype=dtype)
+    t0 = time.perf_counter()
+    ty, kz, _ = B.autotune()
+    t_tune = time.perf_counter() - t0
+    B.advance(2)                                   # warm-up (captures the graphs)
+    B.sync()
+    for S, S0 in zip(states, init):
+        S.copy_(S0)
+    B.close()
+    B = Batch(dims, states, bc="periodic", dtype=dtype)
+    B.set_launch(ty, kz)
+    B.advance(1)
+    B.sync()
+    for S, S0 in zip(states, init):
+        S.copy_(S0)
+    B.close()
+    B = Batch(dims, states, bc="periodic", dtype=dtype)
+    B.set_launch(ty, kz)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    B.advance(steps)
+    ev1.record()
+    B.sync()
+    torch.cuda.synchronize()
+    ms_batch = ev0.elapsed_time(ev1)
+    B.close()
+    # one problem at a time, default launch shape of the single-problem path
+    seq = [S.clone() for S in init]
+    for F, S in zip(handles, seq):
+        F.advance(S, 1)
+    torch.cuda.synchronize()
+    seq = [S.clone() for S in init]
+    torch.cuda.synchronize()
+    ev0.record()
+    for F, S in zip(handles, seq):
+        F.advance(S, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1)
+    for F in handles:
+        F.close()
+    return {
+        "workload": f"{count} random-plane Riemann problems, meshes 32..160 per axis "
+                    f"(seed {seed}), {cells / 1e6:.1f} M cells, periodic, {steps} steps, "
+                    "per-problem device dt",
+        "value": cells * steps / (ms_batch / 1e3), "unit": "cell-updates/s",
+        "ms_per_step": ms_batch / steps,
+        "sequential_value": cells * steps / (ms_seq / 1e3),
+        "speedup_vs_one_at_a_time": round(ms_seq / ms_batch, 3),
+        "launch": {"tile_y": ty, "chunk_z": kz, "autotune_s": round(t_tune, 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,8 +376,8 @@ def main():
     ap.add_argument("--chunk-z", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the FP64 form only")
-    ap.add_argument("--forms", default="f32,learned",
-                    help="comma list of the forms to run beside FP64: f32, learned")
+    ap.add_argument("--forms", default="f32,batch,learned",
+                    help="comma list of the forms to run beside FP64: f32, batch, learned")
     ap.add_argument("--learned-iters", type=int, default=8000,
                     help="Adam steps of the learned form's training")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -384,6 +454,10 @@ def main():
                         "steps (same dt sequence)",
             "roofline": roof32, "alu": alu32}
     del U64
+    if "batch" in forms:
+        print("bench: batched form", file=sys.stderr, flush=True)
+        line["forms"]["batch_f64"] = batched_form("f64")
+        line["forms"]["batch_f32"] = batched_form("f32")
     if "learned" in forms:
         print("bench: learned-correction form (training, then timing)", file=sys.stderr, flush=True)
         line["forms"]["learned"] = learned_form(iters=args.learned_iters)

@@ -45,6 +45,15 @@ SIGNATURES = [
     ("gs_fluid_workspace_bytes", _LL, [_I, _I, _I, _I]),
     ("gs_fluid_destroy", None, [_VP]),
     ("gs_fluid_last_error", ctypes.c_char_p, [_VP]),
+    # batched form (include/gs_batch.h)
+    ("gs_batch_create", _I, [_I, _VP, _D, _D, _I, _I, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("gs_batch_set_launch", _I, [_VP, _I, _I]),
+    ("gs_batch_autotune", _I, [_VP, ctypes.c_char_p, _PI, _PI, _PI]),
+    ("gs_batch_advance", _I, [_VP, _I, _D, _I]),
+    ("gs_batch_times", _I, [_VP, _PD]),
+    ("gs_batch_sync", _I, [_VP]),
+    ("gs_batch_destroy", None, [_VP]),
+    ("gs_batch_last_error", ctypes.c_char_p, [_VP]),
     # learned-correction network (include/gs_cnn.h)
     ("gs_cnn_param_count", _I, []),
     ("gs_cnn_create", _I, [_I, _I, _I, _I, _D, _VP, ctypes.POINTER(_VP)]),

@@ -9,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", f) for f in ("gs_fluid.h", "gs_cnn.h")]
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("gs_fluid.h", "gs_cnn.h", "gs_batch.h")]
 
 lib_mod = pytest.importorskip("paper_1812_07977_amd._lib")
 
@@ -26,7 +26,7 @@ def _declared():
     for path in HEADERS:
         text = open(path).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"\b(gs_(?:fluid|cnn)_\w+)\s*\(", text))
+        names |= set(re.findall(r"\b(gs_(?:fluid|cnn|batch)_\w+)\s*\(", text))
     return sorted(names)
 
 

@@ -142,3 +142,19 @@ def random_plane(nx, ny, nz, seed, gamma=GAMMA, v=(0.0, 0.0, 0.0)):
     rho = np.where(mask, 1.0, 1.0 / r_rho)
     p = np.where(mask, 1.0, 1.0 / r_p)
     return conserved(rho, *v, p, (nz, ny, nx), gamma)
+
+
+def random_batch_dims(count, seed, lo=32, hi=160):
+    """Mesh sizes of a batch: each of nx, ny, nz drawn uniformly from the
+    integers [lo, hi] with numpy's default_rng(seed) (non-cubic meshes)."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in rng.integers(lo, hi + 1, 3)) for _ in range(count)]
+
+
+def random_batch(count, seed, lo=32, hi=160, gamma=GAMMA):
+    """A batch of seeded random-plane Riemann problems: mesh sizes from
+    random_batch_dims(count, seed, lo, hi); problem i is
+    random_plane(nx, ny, nz, seed=1000 * seed + i) on its own mesh."""
+    dims = random_batch_dims(count, seed, lo, hi)
+    return dims, [random_plane(nx, ny, nz, seed=1000 * seed + i, gamma=gamma)
+                  for i, (nx, ny, nz) in enumerate(dims)]
