@@ -260,14 +260,6 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
             WLz[v] = fmaR(T(0.5), minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
     }
 
-    // U(n) (and, FP32, its compensation and the first increment) of the
-    // next plane in stage 2, prefetched
-    T Uon[NV], Con[NV], Don[NV];
-    if (STAGE == 2) load5(Un + (long long)z0 * g.plane, F, own, Uon);
-    if (KAHAN) {
-        load5(Cn + (long long)z0 * g.plane, F, own, Con);
-        load5(D0 + (long long)z0 * g.plane, F, own, Don);
-    }
 
     for (int z = z0; z < z1; ++z) {
         // stage the plane's primitives in LDS
@@ -332,26 +324,18 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         }
         __syncthreads();
 
-        // prefetch plane z+3 of the own column and of the halo, and U(n)
-        // (with its compensation) of the next plane in stage 2
+        // prefetch plane z+3 of the own column and of the halo; in stage 2
+        // load U(n) (FP32: with its compensation and the first increment)
+        // of this plane for the combine below.  Loading these one plane
+        // ahead instead would keep 10-15 more registers live and cost the
+        // FP64 second substep its third wave per SIMD.
         T Uk3[NV], Uo[NV], Co[NV], Do[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
         if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
-        if (STAGE == 2) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Uo[v] = Uon[v];
-            if (z + 1 < z1) load5(Un + (long long)(z + 1) * g.plane, F, own, Uon);
-        }
+        if (STAGE == 2) load5(Un + (long long)z * g.plane, F, own, Uo);
         if (KAHAN) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                Co[v] = Con[v];
-                Do[v] = Don[v];
-            }
-            if (z + 1 < z1) {
-                load5(Cn + (long long)(z + 1) * g.plane, F, own, Con);
-                load5(D0 + (long long)(z + 1) * g.plane, F, own, Don);
-            }
+            load5(Cn + (long long)z * g.plane, F, own, Co);
+            load5(D0 + (long long)z * g.plane, F, own, Do);
         }
 
         // z-face above the own cell, from the register queue
