@@ -188,13 +188,14 @@ def f32_error(U0, n, dts, U64):
     return l1, linf
 
 
-def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
+def learned_form(n=128, iters=8000, eval_steps=200, stride=10, eval_seeds=(99, 98, 97)):
     """The learned-correction form on the coarse/fine pair n^3 / (2n)^3
     (periodic unit cubes): train the network on fine FP64 runs restricted
     2:1 (seeded random-plane Riemann problems and sine waves), then time, to
     the same end time on a held-out Riemann problem, the fine FP64 solve, the
     plain coarse FP32 solve and the corrected coarse FP32 solve, and measure
-    both coarse solves' L1 errors against the restricted fine solve."""
+    both coarse solves' L1 errors against the restricted fine solve on each
+    held-out problem (timings from the first)."""
     import numpy as np
     import torch
     import workloads as wl
@@ -213,8 +214,8 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
         v = tuple(float(x) for x in rng.uniform(-1, 1, 3))
         return wl.sine_wave(f, f, f, k=k, v=v, amp=0.2)
 
-    states = [torch.from_numpy(wl.random_plane(f, f, f, seed=s)).cuda() for s in range(6)]
-    states += [torch.from_numpy(sine(s)).cuda() for s in (100, 101)]
+    states = [torch.from_numpy(wl.random_plane(f, f, f, seed=s)).cuda() for s in range(12)]
+    states += [torch.from_numpy(sine(s)).cuda() for s in (100, 101, 102, 103)]
     # training states spread over the whole evaluated time window
     inputs, raw = L.generate_samples(net, states, eval_steps, stride=stride)
     mu, sigma, tau = L.normalisation(inputs, raw)
@@ -224,22 +225,17 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
     del raw
     L.train(net, inputs, targets, iters, lr=3e-4)
     del inputs, targets
-    alpha, blend_errs = L.fit_blend(net, states[:2], eval_steps // 2,
-                                    alphas=(0.0, 0.25, 0.5, 0.75, 1.0))
     del states
+    # blend factor fitted on validation problems (neither trained on nor
+    # evaluated), so that a correction that does not generalise is damped
+    val = [torch.from_numpy(wl.random_plane(f, f, f, seed=s)).cuda() for s in (50, 51, 52)]
+    alpha, blend_errs = L.fit_blend(net, val, eval_steps, alphas=(0.0, 0.25, 0.5, 0.75, 1.0))
+    del val
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    U0 = torch.from_numpy(wl.random_plane(f, f, f, seed=eval_seed)).cuda()
     Cp = Fluid((n,) * 3, bc="periodic", dtype="f32")
-    # the time grid: the plain coarse run's own CFL steps
-    plain = net.restrict(U0)
-    dts = []
-    for _ in range(eval_steps):
-        dt = Cp.dt(plain)
-        dts.append(dt)
-        Cp.step(plain, dt)
-    T = float(sum(dts))
+    Ff = Fluid((f,) * 3, bc="periodic", dtype="f64")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def timed(fn):
@@ -250,46 +246,69 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=5, eval_seed=99):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1)
 
-    plain = net.restrict(U0)
-    ms_plain = timed(lambda: [Cp.step(plain, dt) for dt in dts])
-    corr = net.restrict(U0)
-    a0, f0 = net.counts()
+    per_seed = []
+    for seed in eval_seeds:
+        U0 = torch.from_numpy(wl.random_plane(f, f, f, seed=seed)).cuda()
+        # the time grid: the plain coarse run's own CFL steps
+        plain = net.restrict(U0)
+        dts = []
+        for _ in range(eval_steps):
+            dt = Cp.dt(plain)
+            dts.append(dt)
+            Cp.step(plain, dt)
+        T = float(sum(dts))
+        plain = net.restrict(U0)
+        ms_plain = timed(lambda: [Cp.step(plain, dt) for dt in dts])
+        corr = net.restrict(U0)
+        a0, f0 = net.counts()
 
-    def corrected():
-        for dt in dts:
-            Cp.step(corr, dt)
-            if alpha > 0:
-                net.correct(corr)
-    ms_corr = timed(corrected)
-    a1, f1 = net.counts()
-    # the fine FP64 solve to the same time: count its steps once, then time
-    Ff = Fluid((f,) * 3, bc="periodic", dtype="f64")
-    Uf = U0.clone()
-    log = torch.zeros(8 * eval_steps, dtype=torch.float64, device="cuda")
-    Ff.advance(Uf, 8 * eval_steps, T, log)
-    Ff.sync()
-    nfine = int((log > 0).sum())
-    Uf = U0.clone()
-    Ff.time = 0.0
-    ms_fine = timed(lambda: Ff.advance(Uf, nfine, T))
-    errs = L._errors(net, Uf, plain, corr)
+        def corrected():
+            for dt in dts:
+                Cp.step(corr, dt)
+                if alpha > 0:
+                    net.correct(corr)
+        ms_corr = timed(corrected)
+        a1, f1 = net.counts()
+        # the fine FP64 solve to the same time: count its steps once, then time
+        Uf = U0.clone()
+        log = torch.zeros(8 * eval_steps, dtype=torch.float64, device="cuda")
+        Ff.time = 0.0
+        Ff.advance(Uf, 8 * eval_steps, T, log)
+        Ff.sync()
+        nfine = int((log > 0).sum())
+        Uf = U0.clone()
+        Ff.time = 0.0
+        ms_fine = timed(lambda: Ff.advance(Uf, nfine, T))
+        errs = L._errors(net, Uf, plain, corr)
+        per_seed.append(dict(seed=seed, T=T, ms_plain=ms_plain, ms_corr=ms_corr, ms_fine=ms_fine,
+                             nfine=nfine, applied=a1 - a0, fallbacks=f1 - f0,
+                             corr=[round(x, 5) for x in errs["l1_corrected"]],
+                             plain=[round(x, 5) for x in errs["l1_plain"]]))
+        del U0, Uf, plain, corr
     Ff.close()
     Cp.close()
     net.close()
+    first = per_seed[0]
+    ratios = [float(np.mean(r["corr"]) / np.mean(r["plain"])) for r in per_seed]
     return {
-        "workload": f"held-out random-plane Riemann problem (seed {eval_seed}), {n}^3 coarse FP32 "
-                    f"+ network vs {f}^3 FP64, {eval_steps} coarse steps to t = {T:.5f}",
-        "value": n ** 3 * eval_steps / (ms_corr / 1e3), "unit": "coarse cell-updates/s",
-        "ms_corrected": round(ms_corr, 2), "ms_plain_coarse": round(ms_plain, 2),
-        "ms_fine_f64": round(ms_fine, 2), "fine_steps": nfine,
-        "speedup_vs_f64": round(ms_fine / ms_corr, 3),
-        "l1_rel_err_corrected": [round(x, 5) for x in errs["l1_corrected"]],
-        "l1_rel_err_plain_coarse": [round(x, 5) for x in errs["l1_plain"]],
+        "workload": f"held-out random-plane Riemann problems (seeds {list(eval_seeds)}), {n}^3 coarse "
+                    f"FP32 + network vs {f}^3 FP64, {eval_steps} coarse steps each (timings: seed "
+                    f"{first['seed']}, to t = {first['T']:.5f})",
+        "value": n ** 3 * eval_steps / (first["ms_corr"] / 1e3), "unit": "coarse cell-updates/s",
+        "ms_corrected": round(first["ms_corr"], 2), "ms_plain_coarse": round(first["ms_plain"], 2),
+        "ms_fine_f64": round(first["ms_fine"], 2), "fine_steps": first["nfine"],
+        "speedup_vs_f64": round(first["ms_fine"] / first["ms_corr"], 3),
+        "l1_rel_err_corrected": first["corr"],
+        "l1_rel_err_plain_coarse": first["plain"],
         "l1_fields": ["rho", "momentum (all components)", "E"],
         "error_vs": f"the {f}^3 FP64 solve restricted 2:1 at the same time",
-        "corrections_applied": a1 - a0, "fallbacks": f1 - f0, "blend": alpha,
+        "per_seed": [{k: r[k] for k in ("seed", "corr", "plain", "applied", "fallbacks")}
+                     for r in per_seed],
+        "mean_l1_ratio_corrected_over_plain": round(float(np.mean(ratios)), 4),
+        "corrections_applied": first["applied"], "fallbacks": first["fallbacks"], "blend": alpha,
         "blend_fit_l1": {str(k): round(v, 5) for k, v in blend_errs.items()},
-        "training": f"{iters} Adam steps on 8 trajectories x {eval_steps // stride} states "
+        "blend_fit_on": "random-plane Riemann problems, seeds 50-52 (validation)",
+        "training": f"{iters} Adam steps on 16 trajectories x {eval_steps // stride} states "
                     f"(every {stride}th of {eval_steps} steps; {f}^3 FP64 restricted), "
                     f"{t_train:.1f} s incl. data",
     }

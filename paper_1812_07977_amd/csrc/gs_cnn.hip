@@ -29,6 +29,7 @@
 // order by a second kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -84,6 +85,43 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// two FP32 values -> packed BF16 pair (low = a), round to nearest even
+// (v_cvt_pk_bf16_f32; the same result as f2bf for finite values)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16(float a, float b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2{a, b}), bf16x2));
+}
+
+// value of lane (l ^ 1) / (l ^ 2) of the same quad (DPP quad permutations)
+__device__ __forceinline__ float quad_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_xor2(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+
+// 4 x 4 transpose within each quad of lanes: lane q of the quad holds
+// v[i] = M[i][q] on entry and v[j] = M[q][j] on return.  Two exchange
+// stages, with lane q ^ 1 (entries whose index differs from q in bit 0),
+// then with lane q ^ 2 (bit 1).
+__device__ __forceinline__ void quad_transpose(float (&v)[4], int q)
+{
+    const bool b0 = (q & 1) != 0, b1 = (q & 2) != 0;
+    float r0 = quad_xor1(b0 ? v[0] : v[1]), r1 = quad_xor1(b0 ? v[2] : v[3]);
+    const float u0 = b0 ? r0 : v[0], u1 = b0 ? v[1] : r0;
+    const float u2 = b0 ? r1 : v[2], u3 = b0 ? v[3] : r1;
+    r0 = quad_xor2(b1 ? u0 : u2);
+    r1 = quad_xor2(b1 ? u1 : u3);
+    v[0] = b1 ? r0 : u0;
+    v[1] = b1 ? r1 : u1;
+    v[2] = b1 ? u2 : r0;
+    v[3] = b1 ? u3 : r1;
+}
+
 // ---------------------------------------------------------------------------
 // weight packing
 // ---------------------------------------------------------------------------
@@ -134,87 +172,293 @@ struct ConvGeom {
     int nx, ny, nz;
     int periodic;
     int ntx, nty;   // 16 x 16 tiles
-    int kz;         // planes per workgroup
+    int kz;         // planes per work item
+    int items;      // work items: tiles x z-chunks
 };
+
+// LDS staging of the convolution input: the 16 x 16 output tile plus a
+// one-cell halo (18 x 18 cells) per plane, in a ring of four plane slots:
+// planes z-1, z, z+1 are read while plane z+2 is written into the fourth,
+// so one barrier per plane suffices.  Within a plane, 16-byte chunk c
+// (channels 8c .. 8c+7) of halo cell k sits at slot c CP + k: the 16 lanes
+// of a quarter-wave read 16 consecutive cells of one chunk, 256 contiguous
+// bytes, which the gfx950 LDS serves without bank conflicts (a cell-major
+// layout with an 80-byte cell stride measured two cycles per read instead of
+// one).  CP = 336 (a multiple of 16 slots) for four chunks.  The boundary
+// map is applied once, while staging.
+constexpr int HT = 18;
+constexpr int RING = 4;
+constexpr int CONV_ROWS = 2;                       // tile rows per wave
+constexpr int CONV_THREADS = 64 * 16 / CONV_ROWS;  // 8 waves: two per SIMD
+
+template <int CINP>
+struct Stage {
+    static constexpr int CH = CINP / 8;                  // 16-byte chunks per cell
+    static constexpr int CP = (CINP == 32) ? 336 : HT * HT;  // slots per chunk plane
+    static constexpr int PLANE = CH * CP;                // slots per plane
+    static constexpr int CHUNKS = HT * HT * CH;
+    static constexpr int LOADS = (CHUNKS + CONV_THREADS - 1) / CONV_THREADS;
+};
+
+// halo index i in [-1, n + 15] -> mesh index.  Positions past n feed only
+// outputs outside the mesh (ragged tiles), so any valid index serves.
+__device__ __forceinline__ int halo_map(int i, int n, int periodic)
+{
+    if (i > n) i = n;
+    if (periodic) return i < 0 ? i + n : (i >= n ? i - n : i);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <int CINP>
+__device__ __forceinline__ void stage_fetch(const u16* __restrict__ X, const ConvGeom& g, int x0,
+                                            int y0, int p, u32x4 (&r)[Stage<CINP>::LOADS])
+{
+    using S = Stage<CINP>;
+    const int zs = halo_map(p, g.nz, g.periodic);
+#pragma unroll
+    for (int k = 0; k < S::LOADS; ++k) {
+        const int e = threadIdx.x + k * CONV_THREADS;
+        if (e < S::CHUNKS) {
+            const int cell = e / S::CH, c = e % S::CH;
+            const int hy = cell / HT, hx = cell - hy * HT;
+            const int ys = halo_map(y0 - 1 + hy, g.ny, g.periodic);
+            const int xs = halo_map(x0 - 1 + hx, g.nx, g.periodic);
+            const long long v = ((long long)zs * g.ny + ys) * g.nx + xs;
+            r[k] = *(const u32x4*)(X + v * CINP + 8 * c);
+        }
+    }
+}
+
+template <int CINP>
+__device__ __forceinline__ void stage_store(u32x4* __restrict__ plane,
+                                            const u32x4 (&r)[Stage<CINP>::LOADS])
+{
+    using S = Stage<CINP>;
+#pragma unroll
+    for (int k = 0; k < S::LOADS; ++k) {
+        const int e = threadIdx.x + k * CONV_THREADS;
+        if (e < S::CHUNKS) {
+            const int cell = e / S::CH, c = e % S::CH;
+            plane[c * S::CP + cell] = r[k];
+        }
+    }
+}
 
 // X: CL input with CINP channels.  Wp: fragment-packed weights.  Output per
 // EPI: RELU_BF16 -> CL BF16 [v][16 NB] of max(acc + bias, 0); F32_SOA ->
 // FP32 [co][v] for co < cout_valid, acc + bias; MASK_BF16 -> CL BF16 of acc
 // where mask (CL BF16, same shape) is positive, else 0.
+//
+// Persistent: workgroup b takes work items b, b + grid, ...; an item is one
+// 16 x 16 tile over kz consecutive planes.  Eight waves (two per SIMD, so
+// one's products overlap the other's stores and waits) share the weights
+// and the ring; wave w computes rows 2w, 2w+1 of the tile (two M-blocks of
+// 16 cells) for all NB N-blocks, reading its operand fragments from LDS one
+// group ahead of the products that use them: for 32 input channels a group
+// is the three taps (dz, 0..2, dx), whose A fragments are four rows (the
+// same rows shifted by dy); for 8 input channels a group is one K-block of
+// four taps.  The next plane of the ring
+// is fetched into registers before the products of the current plane and
+// written to LDS after them.
 template <int CINP, int NB, int EPI>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(CONV_THREADS)
 conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* __restrict__ bias,
             void* __restrict__ out, const u16* __restrict__ mask, ConvGeom g, int cout_valid)
 {
+    using S = Stage<CINP>;
     constexpr int KB = (CINP == 32) ? TAPS : 7;
     constexpr int COUT = 16 * NB;
     __shared__ u32x4 Wl[KB * NB * 64];
-    for (int i = threadIdx.x; i < KB * NB * 64; i += THREADS) Wl[i] = ((const u32x4*)Wp)[i];
-    __syncthreads();
+    __shared__ u32x4 In[RING * S::PLANE];
+    for (int i = threadIdx.x; i < KB * NB * 64; i += CONV_THREADS) Wl[i] = ((const u32x4*)Wp)[i];
 
+    constexpr int RW = CONV_ROWS;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int xl = l & 15, grp = l >> 4;
     const int ntile = g.ntx * g.nty;
-    const int tile = blockIdx.x % ntile, chunk = blockIdx.x / ntile;
-    const int x0 = (tile % g.ntx) * 16, y0 = (tile / g.ntx) * 16;
-    const int z0 = chunk * g.kz, z1 = min(z0 + g.kz, g.nz);
     const long long ncell = (long long)g.nx * g.ny * g.nz;
-    const int xa = x0 + xl;  // the cell whose A row this lane loads
-
-    for (int z = z0; z < z1; ++z) {
-        f32x4 acc[4][NB];
+    // per-lane LDS slot of its A fragment for halo offset (0, 0): row RW wave
+    // (+ r + dy), column xl (+ dx), chunk grp
+    const int lane_off = (RW * wave) * HT + xl + ((CINP == 32) ? grp * S::CP : 0);
+    // CINP = 8: K-block kb covers taps 4 kb .. 4 kb + 3, one per lane group
+    int kb_plane[KB], kb_off[KB];
+    if (CINP != 32) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll 3
         for (int kb = 0; kb < KB; ++kb) {
-            int tap = (CINP == 32) ? kb : 4 * kb + grp;
+            int tap = 4 * kb + grp;
             if (tap >= TAPS) tap = 13;  // padding taps carry zero weights
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int zs = wrap_or_clamp(z + dz, g.nz, g.periodic);
-            const int xs = wrap_or_clamp(xa + dx, g.nx, g.periodic);
-            u32x4 a[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ys = wrap_or_clamp(y0 + 4 * wave + r + dy, g.ny, g.periodic);
-                const long long v = ((long long)zs * g.ny + ys) * g.nx + xs;
-                const long long off = (CINP == 32) ? v * 32 + 8 * grp : v * 8;
-                a[r] = *(const u32x4*)(X + off);
-            }
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const u32x4 b = Wl[(kb * NB + nb) * 64 + l];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r][nb] = mfma(a[r], b, acc[r][nb]);
-            }
+            kb_plane[kb] = tap / 9;
+            kb_off[kb] = ((tap / 3) % 3) * HT + tap % 3;
         }
+    }
+    float bv[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) bv[nb] = (EPI == EPI_MASK_BF16) ? 0.0f : bias[16 * nb + xl];
 
-        // epilogue: lane holds D[4 grp + i][xl]: cell x0 + 4 grp + i, channel
-        // 16 nb + xl
+    for (int item = blockIdx.x; item < g.items; item += gridDim.x) {
+        const int tile = item % ntile, chunk = item / ntile;
+        const int x0 = (tile % g.ntx) * 16, y0 = (tile / g.ntx) * 16;
+        const int z0 = chunk * g.kz, z1 = min(z0 + g.kz, g.nz);
+        // planes z0-1 .. z0+1 in one round trip; plane z0+2 stays in flight
+        u32x4 pa[S::LOADS], pb[S::LOADS], pc[S::LOADS];
+        stage_fetch<CINP>(X, g, x0, y0, z0 - 1, pa);
+        stage_fetch<CINP>(X, g, x0, y0, z0, pb);
+        stage_fetch<CINP>(X, g, x0, y0, z0 + 1, pc);
+        stage_store<CINP>(In, pa);
+        stage_store<CINP>(In + S::PLANE, pb);
+        stage_store<CINP>(In + 2 * S::PLANE, pc);
+        if (z0 + 1 < z1) stage_fetch<CINP>(X, g, x0, y0, z0 + 2, pa);
+        __syncthreads();
+        int sb = 0;  // ring slot of plane z-1; z, z+1 follow, the fourth is free
+        // one output plane; cur holds plane z+2 (fetched one plane earlier),
+        // nxt receives plane z+3, so each fetch has two planes of products
+        // to arrive
+        auto plane = [&](const int z, u32x4(&cur)[S::LOADS], u32x4(&nxt)[S::LOADS]) {
+            if (z + 2 < z1) stage_fetch<CINP>(X, g, x0, y0, z + 3, nxt);
+            // after the quad transpose of the epilogue, lane (grp, xl) holds
+            // channels 16 nb + cq .. + 3 of cell x0 + 4 grp + q of each row
+            const int q = xl & 3, cq = xl & ~3;
+            uint2 mk[RW][NB];
+            if (EPI == EPI_MASK_BF16) {
+                const int x = min(x0 + 4 * grp + q, g.nx - 1);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int y = y0 + 4 * wave + r;
+                for (int r = 0; r < RW; ++r) {
+                    const int y = min(y0 + RW * wave + r, g.ny - 1);
+                    const long long v = ((long long)z * g.ny + y) * g.nx + x;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 4 * grp + i;
-                if (x >= g.nx || y >= g.ny) continue;
-                const long long v = ((long long)z * g.ny + y) * g.nx + x;
+                    for (int nb = 0; nb < NB; ++nb)
+                        mk[r][nb] = *(const uint2*)(mask + v * COUT + 16 * nb + cq);
+                }
+            }
+            const u32x4* pl[3] = {In + sb * S::PLANE, In + ((sb + 1) & 3) * S::PLANE,
+                                  In + ((sb + 2) & 3) * S::PLANE};
+
+            f32x4 acc[RW][NB];
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const int co = 16 * nb + xl;
-                    const float s = acc[r][nb][i];
-                    if (EPI == EPI_RELU_BF16) {
-                        ((u16*)out)[v * COUT + co] = f2bf(fmaxf(s + bias[co], 0.0f));
-                    } else if (EPI == EPI_F32_SOA) {
-                        if (co < cout_valid) ((float*)out)[co * ncell + v] = s + bias[co];
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (CINP == 32) {
+                // group q = (dz, dx): rows 0 .. RW+1 of A, B of taps (dz, 0..2, dx)
+                u32x4 fa[2][RW + 2], fb[2][3][NB];
+#pragma unroll
+                for (int q = 0; q <= 9; ++q) {
+                    if (q < 9) {
+                        const int dz = q / 3, dx = q % 3, cur = q & 1;
+                        const u32x4* src = pl[dz] + lane_off + dx;
+#pragma unroll
+                        for (int j = 0; j < RW + 2; ++j) fa[cur][j] = src[j * HT];
+#pragma unroll
+                        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                            for (int nb = 0; nb < NB; ++nb)
+                                fb[cur][dy][nb] = Wl[((dz * 9 + dy * 3 + dx) * NB + nb) * 64 + l];
+                    }
+                    if (q > 0) {
+                        const int prv = (q - 1) & 1;
+#pragma unroll
+                        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                                for (int r = 0; r < RW; ++r)
+                                    acc[r][nb] = mfma(fa[prv][r + dy], fb[prv][dy][nb], acc[r][nb]);
+                    }
+                    if (q > 0 && q < 9) {
+                        // issue the next group's reads first, then this group's products
+                        __builtin_amdgcn_sched_group_barrier(0x100, RW + 2 + 3 * NB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 3 * RW * NB, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                u32x4 fa[2][RW], fb[2][NB];
+#pragma unroll
+                for (int kb = 0; kb <= KB; ++kb) {
+                    if (kb < KB) {
+                        const int cur = kb & 1, dzi = kb_plane[kb];
+                        const u32x4* src =
+                            (dzi == 0 ? pl[0] : (dzi == 1 ? pl[1] : pl[2])) + lane_off + kb_off[kb];
+#pragma unroll
+                        for (int r = 0; r < RW; ++r) fa[cur][r] = src[r * HT];
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) fb[cur][nb] = Wl[(kb * NB + nb) * 64 + l];
+                    }
+                    if (kb > 0) {
+                        const int prv = (kb - 1) & 1;
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                            for (int r = 0; r < RW; ++r) acc[r][nb] = mfma(fa[prv][r], fb[prv][nb], acc[r][nb]);
+                    }
+                    if (kb > 0 && kb < KB) {
+                        __builtin_amdgcn_sched_group_barrier(0x100, RW + NB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, RW * NB, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            if (z + 1 < z1) stage_store<CINP>(In + ((sb + 3) & 3) * S::PLANE, cur);
+
+            // epilogue: lane holds D[4 grp + i][xl]: cell x0 + 4 grp + i,
+            // channel 16 nb + xl
+            if (EPI == EPI_F32_SOA) {
+                // four consecutive cells of channel xl: one 16-byte store
+                // when they are all inside the mesh and aligned
+                const int xa = x0 + 4 * grp;
+                const bool vec = (g.nx & 3) == 0 && xa + 3 < g.nx;
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const int y = y0 + RW * wave + r;
+                    if (y >= g.ny || xl >= cout_valid) continue;
+                    float* o = (float*)out + xl * ncell + ((long long)z * g.ny + y) * g.nx + xa;
+                    const float b0 = bv[0];
+                    if (vec) {
+                        *(f32x4*)o = f32x4{acc[r][0][0] + b0, acc[r][0][1] + b0, acc[r][0][2] + b0,
+                                           acc[r][0][3] + b0};
                     } else {
-                        const bool on = (mask[v * COUT + co] & 0x7FFFu) != 0;
-                        ((u16*)out)[v * COUT + co] = on ? f2bf(s) : (u16)0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (xa + i < g.nx) o[i] = acc[r][0][i] + b0;
+                    }
+                }
+            } else {
+                const int x = x0 + 4 * grp + q;
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const int y = y0 + RW * wave + r;
+                    const long long v = ((long long)z * g.ny + y) * g.nx + x;
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        float t[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            t[i] = (EPI == EPI_RELU_BF16) ? fmaxf(acc[r][nb][i] + bv[nb], 0.0f)
+                                                          : acc[r][nb][i];
+                        quad_transpose(t, q);
+                        uint2 w;
+                        w.x = pack_bf16(t[0], t[1]);
+                        w.y = pack_bf16(t[2], t[3]);
+                        if (EPI == EPI_MASK_BF16) {
+                            // keep a gradient where its mask entry is positive
+                            const uint2 m = mk[r][nb];
+                            const unsigned lo0 = (m.x & 0x7FFFu) ? 0xFFFFu : 0u;
+                            const unsigned hi0 = (m.x & 0x7FFF0000u) ? 0xFFFF0000u : 0u;
+                            const unsigned lo1 = (m.y & 0x7FFFu) ? 0xFFFFu : 0u;
+                            const unsigned hi1 = (m.y & 0x7FFF0000u) ? 0xFFFF0000u : 0u;
+                            w.x &= lo0 | hi0;
+                            w.y &= lo1 | hi1;
+                        }
+                        if (x < g.nx && y < g.ny) *(uint2*)((u16*)out + v * COUT + 16 * nb + cq) = w;
                     }
                 }
             }
+            __syncthreads();  // plane z+2 is in the ring; plane z-1's slot is free
+            sb = (sb + 1) & 3;
+        };
+        for (int z = z0; z < z1; z += 2) {
+            plane(z, pa, pb);
+            if (z + 1 < z1) plane(z + 1, pb, pa);
         }
     }
 }
@@ -790,14 +1034,42 @@ ConvGeom conv_geom(const gs_cnn* h)
     g.ntx = (h->nx + 15) / 16;
     g.nty = (h->ny + 15) / 16;
     const int ntile = g.ntx * g.nty;
-    // aim for >= 2048 workgroups, at least one plane each
-    long long want = (2048 + ntile - 1) / ntile;
+    // about 1024 work items (a few per resident workgroup), each as many
+    // planes as that allows: longer chunks stage fewer halo planes
+    long long want = (1024 + ntile - 1) / ntile;
     int kz = (int)((h->nz + want - 1) / want);
     g.kz = kz < 1 ? 1 : kz;
+    g.items = ntile * ((g.nz + g.kz - 1) / g.kz);
     return g;
 }
 
-int conv_blocks(const ConvGeom& g) { return g.ntx * g.nty * ((g.nz + g.kz - 1) / g.kz); }
+// persistent grid of a convolution kernel: its resident workgroups, at most
+// one per work item
+template <int CINP, int NB, int EPI>
+int conv_grid(const ConvGeom& g)
+{
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, per_cu = 0, cus = 256;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv_kernel<CINP, NB, EPI>,
+                                                         CONV_THREADS, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        resident = per_cu * cus;
+    }
+    return std::min(resident, g.items);
+}
+
+template <int CINP, int NB, int EPI>
+void launch_conv(gs_cnn* h, const ConvGeom& g, const u16* X, const u16* Wp, const float* bias, void* out,
+                 const u16* mask, int cout_valid)
+{
+    hipLaunchKernelGGL((conv_kernel<CINP, NB, EPI>), dim3(conv_grid<CINP, NB, EPI>(g)), dim3(CONV_THREADS), 0,
+                       h->stream, X, Wp, bias, out, mask, g, cout_valid);
+}
 
 hipError_t pack_all(gs_cnn* h)
 {
@@ -821,15 +1093,11 @@ hipError_t pack_all(gs_cnn* h)
 hipError_t forward(gs_cnn* h, const float* U)
 {
     const ConvGeom g = conv_geom(h);
-    const int nb = conv_blocks(g);
     hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(h->ncell)), dim3(THREADS), 0, h->stream, U,
                        h->ncell, h->norm, h->x);
-    hipLaunchKernelGGL((conv_kernel<8, 2, EPI_RELU_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
-                       h->x, h->wf1, h->P + B1_OFF, (void*)h->h1, (const u16*)nullptr, g, HID);
-    hipLaunchKernelGGL((conv_kernel<32, 2, EPI_RELU_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
-                       h->h1, h->wf2, h->P + B2_OFF, (void*)h->h2, (const u16*)nullptr, g, HID);
-    hipLaunchKernelGGL((conv_kernel<32, 1, EPI_F32_SOA>), dim3(nb), dim3(THREADS), 0, h->stream,
-                       h->h2, h->wf3, h->P + B3_OFF, (void*)h->y, (const u16*)nullptr, g, NF);
+    launch_conv<8, 2, EPI_RELU_BF16>(h, g, h->x, h->wf1, h->P + B1_OFF, h->h1, nullptr, HID);
+    launch_conv<32, 2, EPI_RELU_BF16>(h, g, h->h1, h->wf2, h->P + B2_OFF, h->h2, nullptr, HID);
+    launch_conv<32, 1, EPI_F32_SOA>(h, g, h->h2, h->wf3, h->P + B3_OFF, h->y, nullptr, NF);
     return hipGetLastError();
 }
 
@@ -845,7 +1113,6 @@ void bias_grad(gs_cnn* h, const u16* dAv, int C, float* gb)
 hipError_t backward(gs_cnn* h, const float* target)
 {
     const ConvGeom g = conv_geom(h);
-    const int nb = conv_blocks(g);
     const long long n = h->ncell;
     hipLaunchKernelGGL(loss_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, target, n,
                        h->red, h->dY, h->dYv);
@@ -858,8 +1125,7 @@ hipError_t backward(gs_cnn* h, const float* target)
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W3_N)), dim3(THREADS), 0, h->stream,
                        h->wpart, parts, 32, 16, HID, NF, h->G + W3_OFF);
     bias_grad(h, h->dYv, NF, h->G + B3_OFF);
-    hipLaunchKernelGGL((conv_kernel<8, 2, EPI_MASK_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
-                       h->dY, h->wb3, (const float*)nullptr, (void*)h->dA2, h->h2, g, HID);
+    launch_conv<8, 2, EPI_MASK_BF16>(h, g, h->dY, h->wb3, nullptr, h->dA2, h->h2, HID);
     // layer 2
     hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA2, HID, HID,
                        1, h->nx, h->ny, h->nz, 1, h->dA2v);
@@ -870,8 +1136,7 @@ hipError_t backward(gs_cnn* h, const float* target)
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W2_N)), dim3(THREADS), 0, h->stream,
                        h->wpart, parts, 32, 32, HID, HID, h->G + W2_OFF);
     bias_grad(h, h->dA2v, HID, h->G + B2_OFF);
-    hipLaunchKernelGGL((conv_kernel<32, 2, EPI_MASK_BF16>), dim3(nb), dim3(THREADS), 0, h->stream,
-                       h->dA2, h->wb2, (const float*)nullptr, (void*)h->dA1, h->h1, g, HID);
+    launch_conv<32, 2, EPI_MASK_BF16>(h, g, h->dA2, h->wb2, nullptr, h->dA1, h->h1, HID);
     // layer 1
     hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA1, HID, HID,
                        1, h->nx, h->ny, h->nz, 1, h->dA1v);

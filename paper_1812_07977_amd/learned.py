@@ -339,7 +339,8 @@ def train(net, inputs, targets, iters, lr=1e-3, seed=0, log_every=0, augment=Tru
 def fit_blend(net, fine_states, steps, alphas=(0.25, 0.5, 0.75, 1.0), gamma=1.4, cfl=0.5):
     """The factor alpha that scales the applied correction: the one with the
     smallest mean L1 error after `steps` corrected steps over the given
-    (training) trajectories; alpha = 0 (no correction: the plain coarse
+    trajectories (validation problems, not trained on, give an honest
+    choice); alpha = 0 (no correction: the plain coarse
     solve) may be listed.  Sets the net's tau to alpha tau (alpha = 0 keeps
     tau and returns 0: the caller then skips the correction) and returns
     (alpha, {alpha: error})."""
