@@ -7,10 +7,14 @@
 //   * CL (channels-last) BF16 activations: act[v * C + c], v = (z ny + y) nx
 //     + x, C = 8 (the 5 input fields padded with zeros) or 32.  One MFMA
 //     operand fragment of 8 channels of one cell is one 16-byte load.
-//   * VM (voxel-major) BF16 copies for the weight gradient: vm[c][v], and
-//     for a layer input three copies shifted by dx = -1, 0, +1 along x (the
-//     boundary map applied while copying), so that every operand fragment of
-//     8 consecutive cells along x is again one aligned 16-byte load.
+//   * RV (row-blocked, channel-major within a row) BF16 copies for the
+//     weight gradient: element (c, v) of a C-channel array, v = row nx + x
+//     with row = z ny + y, at (row C + c) nx + x; for a layer input three
+//     copies shifted by dx = -1, 0, +1 along x (the boundary map applied
+//     while copying), so that every operand fragment of 8 consecutive cells
+//     along x is one aligned 16-byte load, and the channels a wave reads
+//     together lie within a few kilobytes (a mesh-wide channel-major layout
+//     put them megabytes apart, one page each).
 //   * Weights in fragment order: for K-block kb and N-block nb, lane l holds
 //     the 8 values of the 16x16x32 B operand it feeds: 64 lanes x 16 bytes.
 //
@@ -467,110 +471,213 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
 // weight gradient
 // ---------------------------------------------------------------------------
 
-// CL [v][C] -> VM copies out[s][c][v], c < C16 (channels >= C are zero),
-// copy s shifted by s - (ns == 3 ? 1 : 0) along x.
+// CL [v][C] -> RV copies out[s] of C16 channels (channels >= C are zero),
+// copy s shifted by s - (ns == 3 ? 1 : 0) along x.  One thread per 8
+// consecutive cells of a row (nx a multiple of 8, C of 8): it loads the 10
+// cells x0-1 .. x0+8 as 16-byte chunks of 8 channels and writes each channel
+// of each copy as one 16-byte store of 8 cells.
 __global__ void to_vm_kernel(const u16* __restrict__ in, int C, int C16, int ns, int nx, int ny,
                              int nz, int periodic, u16* __restrict__ out)
 {
     const long long ncell = (long long)nx * ny * nz;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell * ns;
+    const int nx8 = nx / 8;
+    const long long units = ncell / 8;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < units;
          e += (long long)gridDim.x * blockDim.x) {
-        const int s = (int)(e / ncell);
-        const long long v = e - s * ncell;
-        const int x = (int)(v % nx);
-        const long long row = v - x;
-        const int dx = s - (ns == 3 ? 1 : 0);
-        const long long src = row + wrap_or_clamp(x + dx, nx, periodic);
-        for (int c = 0; c < C16; ++c)
-            out[((long long)s * C16 + c) * ncell + v] = (c < C) ? in[src * C + c] : (u16)0;
+        const long long row = e / nx8;
+        const int x0 = (int)(e - row * nx8) * 8;
+        const u16* src = in + row * nx * C;
+        for (int c8 = 0; c8 < C16 / 8; ++c8) {
+            // cells x0-1 .. x0+8: 8 channels each as 4 words
+            unsigned w[10][4];
+#pragma unroll
+            for (int i = 0; i < 10; ++i) {
+                const int xs = wrap_or_clamp(x0 - 1 + i, nx, periodic);
+                u32x4 t = u32x4{0u, 0u, 0u, 0u};
+                if (8 * c8 < C) t = *(const u32x4*)(src + (long long)xs * C + 8 * c8);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[i][q] = t[q];
+            }
+            for (int s = 0; s < ns; ++s) {
+                const int sh = s - (ns == 3 ? 1 : 0);  // copy s holds cell x + sh at x
+                u16* o = out + (long long)s * C16 * ncell + (row * C16 + 8 * c8) * nx + x0;
+#pragma unroll
+                for (int ch = 0; ch < 8; ++ch) {
+                    const int q = ch >> 1, hi = ch & 1;
+                    u32x4 v;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        // cells 2k, 2k+1 of the window start at index 1 + sh
+                        const unsigned a = w[1 + sh + 2 * k][q], b = w[2 + sh + 2 * k][q];
+                        const unsigned lo = hi ? (a >> 16) : (a & 0xFFFFu);
+                        const unsigned hb = hi ? (b & 0xFFFF0000u) : (b << 16);
+                        v[k] = lo | hb;
+                    }
+                    *(u32x4*)(o + (long long)ch * nx) = v;
+                }
+            }
+        }
     }
 }
 
-// Partial weight gradients.  Xs: VM input copies [3][MB 16][v]; dA: VM
-// output gradient [NB 16][v].  Workgroup b handles tap b / splits and the
-// b % splits-th share of the K range (rows z, y and 32-cell x blocks);
-// each wave writes its own partial [MB 16][NB 16].
+// Partial weight gradients.  Xs: RV input copies [3] of MB 16 channels
+// (shifted by dx = -1, 0, +1); dA: RV output gradient of NB 16 channels.  Workgroup b sums over
+// its share of the mesh rows (z, y), for all 27 taps: wave w of its nine
+// handles the taps (dz, dy) = (w / 3 - 1, w % 3 - 1) with dx = -1, 0, +1, so
+// that each operand row is fetched from memory about once and the nine waves
+// reuse it through the caches (per tap, a walk over the whole mesh re-read
+// all operands 27 times).  Each (tap, workgroup) writes one partial
+// [MB 16][NB 16]; a second kernel sums them in a fixed order.
+constexpr int WG_WAVES = 9;
+
 template <int MB, int NB>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(64 * WG_WAVES)
 wgrad_kernel(const u16* __restrict__ Xs, const u16* __restrict__ dA, float* __restrict__ partial,
-             int nx, int ny, int nz, int periodic, int splits)
+             int nx, int ny, int nz, int periodic)
 {
     constexpr int CI16 = 16 * MB, CO16 = 16 * NB;
-    const int tap = blockIdx.x / splits, split = blockIdx.x % splits;
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // the walk over rows is the same for all lanes of a wave: keep it in
+    // scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
     const int xl = l & 15, grp = l >> 4;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int dz = wave / 3 - 1, dy = wave % 3 - 1;
     const long long ncell = (long long)nx * ny * nz;
     const int nxb = nx / 32;
-    const long long steps = (long long)nz * ny * nxb;
-    const long long parts = (long long)splits * 4;
-    const long long me = (long long)split * 4 + wave;
-    const long long beg = steps * me / parts, end = steps * (me + 1) / parts;
+    const long long rows = (long long)nz * ny;
+    const long long parts = gridDim.x, me = blockIdx.x;
+    const long long r0 = rows * me / parts, r1 = rows * (me + 1) / parts;
 
-    f32x4 acc[MB][NB];
+    f32x4 acc[3][MB][NB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const u16* xs_base = Xs + (long long)(dx + 1) * CI16 * ncell;
-    for (long long st = beg; st < end; ++st) {
-        const int xb = (int)(st % nxb);
-        const long long zy = st / nxb;
-        const int y = (int)(zy % ny), z = (int)(zy / ny);
-        const int zs = wrap_or_clamp(z + dz, nz, periodic), ys = wrap_or_clamp(y + dy, ny, periodic);
-        const long long xoff = 32 * xb + 8 * grp;
-        const long long vin = ((long long)zs * ny + ys) * nx + xoff;
-        const long long vout = ((long long)z * ny + y) * nx + xoff;
-        u32x4 a[MB], b[NB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m) a[m] = *(const u32x4*)(xs_base + (16 * m + xl) * ncell + vin);
-#pragma unroll
-        for (int n = 0; n < NB; ++n) b[n] = *(const u32x4*)(dA + (16 * n + xl) * ncell + vout);
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int n = 0; n < NB; ++n) acc[m][n] = mfma(a[m], b[n], acc[m][n]);
+            for (int n = 0; n < NB; ++n) acc[d][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // per-lane channel rows of the operands: A = input copy shifted by dx =
+    // d - 1, B = output gradient; fragment of 8 cells at x offset 8 grp
+    const u16* pa[3][MB];
+    const u16* pb[NB];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+            pa[d][m] = Xs + (long long)d * CI16 * ncell + (16 * m + xl) * nx + 8 * grp;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) pb[n] = dA + (16 * n + xl) * nx + 8 * grp;
+
+    // K steps of 32 cells along each row
+    int z = (int)(r0 / ny), y = (int)(r0 % ny);
+    for (long long r = r0; r < r1; ++r) {
+        const int zi = z + dz, yi = y + dy;
+        const int zs = periodic ? (zi < 0 ? zi + nz : (zi >= nz ? zi - nz : zi)) : min(max(zi, 0), nz - 1);
+        const int ys = periodic ? (yi < 0 ? yi + ny : (yi >= ny ? yi - ny : yi)) : min(max(yi, 0), ny - 1);
+        const long long vin = ((long long)zs * ny + ys) * CI16 * nx;
+        const long long vout = r * CO16 * nx;
+        // two K steps in flight: all their loads, then their products
+        for (int xb = 0; xb < nxb; xb += 2) {
+            constexpr int S2 = 2;
+            u32x4 a[S2][3][MB], b[S2][NB];
+#pragma unroll
+            for (int k = 0; k < S2; ++k) {
+                const int xo = 32 * min(xb + k, nxb - 1);
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m) a[k][d][m] = *(const u32x4*)(pa[d][m] + vin + xo);
+#pragma unroll
+                for (int n = 0; n < NB; ++n) b[k][n] = *(const u32x4*)(pb[n] + vout + xo);
+            }
+            // a step past the row end multiplies zeros (its loads repeat the
+            // last block), which leaves the sums unchanged
+            const bool ok = xb + 1 < nxb;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) b[1][n] = ok ? b[1][n] : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int k = 0; k < S2; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m)
+#pragma unroll
+                        for (int n = 0; n < NB; ++n)
+                            acc[d][m][n] = mfma(a[k][d][m], b[k][n], acc[d][m][n]);
+        }
+        ++y;
+        if (y == ny) {
+            y = 0;
+            ++z;
+        }
     }
     // D[4 grp + i][xl] of block (m, n): input channel 16 m + 4 grp + i,
     // output channel 16 n + xl
-    float* p = partial + ((long long)tap * parts + me) * CI16 * CO16;
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int d = 0; d < 3; ++d) {
+        const int tap = (dz + 1) * 9 + (dy + 1) * 3 + d;
+        float* p = partial + ((long long)tap * parts + me) * CI16 * CO16;
 #pragma unroll
-        for (int n = 0; n < NB; ++n)
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) p[(16 * m + 4 * grp + i) * CO16 + 16 * n + xl] = acc[m][n][i];
-}
-
-// Gradient of the master weights W[cout][cin][27]: sum of the partials of
-// every wave in a fixed order.
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int parts, int ci16, int co16,
-                                    int cin, int cout, float* __restrict__ gW)
-{
-    const int total = cout * cin * TAPS;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int tap = e % TAPS, ci = (e / TAPS) % cin, co = e / (TAPS * cin);
-        const float* p = partial + (long long)tap * parts * ci16 * co16 + ci * co16 + co;
-        float s = 0.0f;
-        for (int k = 0; k < parts; ++k) s += p[(long long)k * ci16 * co16];
-        gW[e] = s;
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    p[(16 * m + 4 * grp + i) * CO16 + 16 * n + xl] = acc[d][m][n][i];
     }
 }
 
-// Bias gradient: sums over cells of the VM BF16 output gradient dA[c][v];
-// workgroup (c, j) sums the j-th of BIAS_CHUNKS shares of channel c, then
-// one thread per channel adds the shares in order.
+// Gradient of the master weights W[cout][cin][27]: sum of the partials of
+// every workgroup in a fixed order.  A workgroup sums 32 entries (ci, co) of
+// one tap, e = (t ci16 + ci) co16 + co, so consecutive threads read
+// consecutive partial entries: each of its 8 thread rows adds one eighth of
+// the partials in order, then the eight sums are added in order.
+constexpr int RED_SPLIT = 8;
+
+__global__ void __launch_bounds__(THREADS)
+wgrad_reduce_kernel(const float* __restrict__ partial, int parts, int ci16, int co16, int cin,
+                    int cout, float* __restrict__ gW)
+{
+    constexpr int EPB = THREADS / RED_SPLIT;  // entries per workgroup
+    __shared__ float sums[RED_SPLIT][EPB];
+    const int total = TAPS * ci16 * co16;
+    const int le = threadIdx.x % EPB, q = threadIdx.x / EPB;
+    const int e = blockIdx.x * EPB + le;
+    float s = 0.0f;
+    if (e < total) {
+        const int tap = e / (co16 * ci16), rem = e - tap * co16 * ci16;
+        const float* p = partial + (long long)tap * parts * ci16 * co16 + rem;
+        const int k0 = parts * q / RED_SPLIT, k1 = parts * (q + 1) / RED_SPLIT;
+        for (int k = k0; k < k1; ++k) s += p[(long long)k * ci16 * co16];
+    }
+    sums[q][le] = s;
+    __syncthreads();
+    if (q == 0 && e < total) {
+        float t = sums[0][le];
+#pragma unroll
+        for (int r = 1; r < RED_SPLIT; ++r) t += sums[r][le];
+        const int co = e % co16, ci = (e / co16) % ci16, tap = e / (co16 * ci16);
+        if (co < cout && ci < cin) gW[(co * cin + ci) * TAPS + tap] = t;
+    }
+}
+
+// Bias gradient: sums over cells of the RV BF16 output gradient dA (C
+// channels); workgroup (c, j) sums the j-th of BIAS_CHUNKS shares of channel
+// c, then one thread per channel adds the shares in order.
 constexpr int BIAS_CHUNKS = 64;
 
 __global__ void __launch_bounds__(THREADS)
-bias_partial_kernel(const u16* __restrict__ dA, long long ncell, float* __restrict__ part)
+bias_partial_kernel(const u16* __restrict__ dA, long long ncell, int C, int nx,
+                    float* __restrict__ part)
 {
     __shared__ float red[THREADS];
     const int c = blockIdx.x / BIAS_CHUNKS, j = blockIdx.x % BIAS_CHUNKS;
     const long long beg = ncell * j / BIAS_CHUNKS, end = ncell * (j + 1) / BIAS_CHUNKS;
     float s = 0.0f;
-    for (long long v = beg + threadIdx.x; v < end; v += THREADS) s += bf2f(dA[c * ncell + v]);
+    for (long long v = beg + threadIdx.x; v < end; v += THREADS) {
+        const int row = (int)(v / nx), x = (int)(v - (long long)row * nx);
+        s += bf2f(dA[((long long)row * C + c) * nx + x]);
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = THREADS / 2; w > 0; w >>= 1) {
@@ -704,10 +811,10 @@ __global__ void restrict_kernel(const double* __restrict__ fine, int nx, int ny,
 }
 
 // MSE loss partials (FP64, one per workgroup) and the output gradient
-// 2 (y - t) / N as BF16, CL [v][8] (channels 5..7 zero) and VM [16][v]
+// 2 (y - t) / N as BF16, CL [v][8] (channels 5..7 zero) and RV (16 channels)
 // (channels 5..15 zero)
 __global__ void __launch_bounds__(THREADS)
-loss_kernel(const float* __restrict__ y, const float* __restrict__ t, long long ncell,
+loss_kernel(const float* __restrict__ y, const float* __restrict__ t, long long ncell, int nx,
             double* __restrict__ partial, u16* __restrict__ dCL, u16* __restrict__ dVM)
 {
     __shared__ double red[THREADS];
@@ -721,10 +828,12 @@ loss_kernel(const float* __restrict__ y, const float* __restrict__ t, long long 
             const float e = y[f * ncell + v] - t[f * ncell + v];
             s += (double)e * (double)e;
             d[f] = f2bf(scale * e);
-            dVM[f * ncell + v] = d[f];
         }
         d[5] = d[6] = d[7] = 0;
-        for (int f = NF; f < 16; ++f) dVM[f * ncell + v] = 0;
+        // RV copy of 16 channels (5 used)
+        const int row = (int)(v / nx), x = (int)(v - (long long)row * nx);
+        u16* o = dVM + (long long)row * 16 * nx + x;
+        for (int f = 0; f < 16; ++f) o[(long long)f * nx] = f < NF ? d[f] : (u16)0;
         u32x4 w;
         w[0] = d[0] | ((unsigned)d[1] << 16);
         w[1] = d[2] | ((unsigned)d[3] << 16);
@@ -969,7 +1078,7 @@ namespace {
 thread_local std::string g_cnn_create_error;
 
 constexpr int RED_BLOCKS = 512;
-constexpr int WG_SPLITS = 64;  // workgroups per tap in the weight gradient
+constexpr int WG_PARTS = 512;  // workgroups (partial sums per tap) of the weight gradient
 
 }  // namespace
 
@@ -988,7 +1097,7 @@ struct gs_cnn {
     // activations (CL): input x (8), h1, h2 (32); output y, FP32 SoA
     u16 *x, *h1, *h2;
     float* y;
-    // training: gradients dY (CL 8, VM 16), dA2, dA1 (CL 32, VM 32), VM
+    // training: gradients dY (CL 8, RV 16), dA2, dA1 (CL 32, RV 32), RV
     // shifted copies of x (16 ch), h1, h2 (32 ch)
     u16 *dY, *dYv, *dA2, *dA2v, *dA1, *dA1v, *xs, *h1s, *h2s;
     float* wpart;   // weight-gradient partials
@@ -1101,10 +1210,11 @@ hipError_t forward(gs_cnn* h, const float* U)
     return hipGetLastError();
 }
 
-void bias_grad(gs_cnn* h, const u16* dAv, int C, float* gb)
+// bias gradients of the first C of the Cs channels of an RV array
+void bias_grad(gs_cnn* h, const u16* dAv, int C, int Cs, float* gb)
 {
     hipLaunchKernelGGL(bias_partial_kernel, dim3(C * BIAS_CHUNKS), dim3(THREADS), 0, h->stream, dAv,
-                       h->ncell, h->bpart);
+                       h->ncell, Cs, h->nx, h->bpart);
     hipLaunchKernelGGL(bias_final_kernel, dim3(1), dim3(64), 0, h->stream, h->bpart, C, gb);
 }
 
@@ -1114,39 +1224,40 @@ hipError_t backward(gs_cnn* h, const float* target)
 {
     const ConvGeom g = conv_geom(h);
     const long long n = h->ncell;
-    hipLaunchKernelGGL(loss_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, target, n,
+    hipLaunchKernelGGL(loss_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, h->y, target, n, h->nx,
                        h->red, h->dY, h->dYv);
     // layer 3: dW3 from h2 and dY; dH2 = conv(dY, mirrored W3) masked by h2
-    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->h2, HID,
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n / 8)), dim3(THREADS), 0, h->stream, h->h2, HID,
                        HID, 3, h->nx, h->ny, h->nz, 1, h->h2s);
-    const int parts = WG_SPLITS * 4;
-    hipLaunchKernelGGL((wgrad_kernel<2, 1>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
-                       h->h2s, h->dYv, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W3_N)), dim3(THREADS), 0, h->stream,
+    const int parts = WG_PARTS;
+    const int rgrid = TAPS * 32 * 32 / (THREADS / RED_SPLIT);  // 32 entries per workgroup
+    hipLaunchKernelGGL((wgrad_kernel<2, 1>), dim3(WG_PARTS), dim3(64 * WG_WAVES), 0, h->stream,
+                       h->h2s, h->dYv, h->wpart, h->nx, h->ny, h->nz, 1);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(rgrid), dim3(THREADS), 0, h->stream,
                        h->wpart, parts, 32, 16, HID, NF, h->G + W3_OFF);
-    bias_grad(h, h->dYv, NF, h->G + B3_OFF);
+    bias_grad(h, h->dYv, NF, 16, h->G + B3_OFF);
     launch_conv<8, 2, EPI_MASK_BF16>(h, g, h->dY, h->wb3, nullptr, h->dA2, h->h2, HID);
     // layer 2
-    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA2, HID, HID,
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n / 8)), dim3(THREADS), 0, h->stream, h->dA2, HID, HID,
                        1, h->nx, h->ny, h->nz, 1, h->dA2v);
-    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->h1, HID,
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n / 8)), dim3(THREADS), 0, h->stream, h->h1, HID,
                        HID, 3, h->nx, h->ny, h->nz, 1, h->h1s);
-    hipLaunchKernelGGL((wgrad_kernel<2, 2>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
-                       h->h1s, h->dA2v, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W2_N)), dim3(THREADS), 0, h->stream,
+    hipLaunchKernelGGL((wgrad_kernel<2, 2>), dim3(WG_PARTS), dim3(64 * WG_WAVES), 0, h->stream,
+                       h->h1s, h->dA2v, h->wpart, h->nx, h->ny, h->nz, 1);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(rgrid), dim3(THREADS), 0, h->stream,
                        h->wpart, parts, 32, 32, HID, HID, h->G + W2_OFF);
-    bias_grad(h, h->dA2v, HID, h->G + B2_OFF);
+    bias_grad(h, h->dA2v, HID, HID, h->G + B2_OFF);
     launch_conv<32, 2, EPI_MASK_BF16>(h, g, h->dA2, h->wb2, nullptr, h->dA1, h->h1, HID);
     // layer 1
-    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, h->dA1, HID, HID,
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n / 8)), dim3(THREADS), 0, h->stream, h->dA1, HID, HID,
                        1, h->nx, h->ny, h->nz, 1, h->dA1v);
-    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n * 3)), dim3(THREADS), 0, h->stream, h->x, 8, 16,
+    hipLaunchKernelGGL(to_vm_kernel, dim3(grid_for(n / 8)), dim3(THREADS), 0, h->stream, h->x, 8, 16,
                        3, h->nx, h->ny, h->nz, 1, h->xs);
-    hipLaunchKernelGGL((wgrad_kernel<1, 2>), dim3(TAPS * WG_SPLITS), dim3(THREADS), 0, h->stream,
-                       h->xs, h->dA1v, h->wpart, h->nx, h->ny, h->nz, 1, WG_SPLITS);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(W1_N)), dim3(THREADS), 0, h->stream,
+    hipLaunchKernelGGL((wgrad_kernel<1, 2>), dim3(WG_PARTS), dim3(64 * WG_WAVES), 0, h->stream,
+                       h->xs, h->dA1v, h->wpart, h->nx, h->ny, h->nz, 1);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(rgrid), dim3(THREADS), 0, h->stream,
                        h->wpart, parts, 16, 32, NF, HID, h->G + W1_OFF);
-    bias_grad(h, h->dA1v, HID, h->G + B1_OFF);
+    bias_grad(h, h->dA1v, HID, HID, h->G + B1_OFF);
     return hipGetLastError();
 }
 
@@ -1233,7 +1344,7 @@ int gs_cnn_create(int nx, int ny, int nz, int bc, double gamma, void* stream, gs
         {(void**)&h->dA1, (size_t)n * 32 * 2}, {(void**)&h->dA1v, (size_t)n * 32 * 2},
         {(void**)&h->xs, (size_t)n * 3 * 16 * 2}, {(void**)&h->h1s, (size_t)n * 3 * 32 * 2},
         {(void**)&h->h2s, (size_t)n * 3 * 32 * 2},
-        {(void**)&h->wpart, (size_t)TAPS * WG_SPLITS * 4 * 32 * 32 * 4},
+        {(void**)&h->wpart, (size_t)TAPS * WG_PARTS * 32 * 32 * 4},
         {(void**)&h->bpart, (size_t)32 * BIAS_CHUNKS * 4},
         {(void**)&h->red, RED_BLOCKS * 2 * NF * 8}, {(void**)&h->cand, (size_t)n * 2 * NF * 4},
         {(void**)&h->cs, sizeof(CorrState)},
