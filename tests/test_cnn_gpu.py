@@ -133,10 +133,13 @@ def test_forward_random_weights_within_fp32_accumulation_bound():
     assert np.median(err / absum) < 1e-3
 
 
-def test_gradients_match_the_oracle():
-    shape = (32, 8, 8)
+@pytest.mark.parametrize("shape", [(32, 8, 8), (96, 8, 6)])
+def test_gradients_match_the_oracle(shape):
+    # (96, 8, 6): three 32-cell blocks per row (the weight-gradient kernel
+    # takes two per step, so the second of the last pair is masked) and
+    # fewer rows than workgroups (some sum nothing)
     nx, ny, nz = shape
-    _say("case: cnn gradients 32x8x8 periodic")
+    _say(f"case: cnn gradients {nx}x{ny}x{nz} periodic")
     from paper_1812_07977_amd.learned import split_params
     import torch
     rng = np.random.default_rng(12)
