@@ -14,8 +14,13 @@ starts: the smooth case rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (1,1,1), p = 1
 
 Prints one JSON line with the cell-update rate, the roofline of the dominant
 kernel (per-launch algorithmic HBM bytes over its average event-timed
-duration, against the 8 TB/s HBM3E peak) and the CPU oracle timed on a
-bounded sample on the host cores.  Under "forms" the FP32 form is timed the
+duration, against the 8 TB/s HBM3E peak and against a measured
+device-to-device copy) and the CPU oracle timed on a bounded sample on the
+host cores (all threads; then one eighth of them and one, on a smaller
+sample).  After the reported block of steps, four more blocks of the same
+length give the spread of the rate (reported with their median), and 20
+steps of the host-synchronised path (gs_fluid_dt, then gs_fluid_step) give
+its rate.  Under "forms" the FP32 form is timed the
 same way on the same input, with its speedup over FP64 and its L1 and
 L-infinity error per field against the FP64 solution of the same input after
 the same steps (the FP32 run is driven with the FP64 run's time steps; the
@@ -86,23 +91,39 @@ def make_input(size, case):
 
 def cpu_baseline(case, size=256, steps=10):
     """The oracle as it stands, on a bounded sample: the same case on a
-    size^3 mesh for `steps` RK2 steps, using every host core OpenMP gives it."""
+    size^3 mesh for `steps` RK2 steps, using every host core OpenMP gives it;
+    then, on a 128^3 sample of 2 steps, with one eighth of those threads (the
+    host share of one GPU of eight) and with one thread."""
     import oracle
-    U = make_input(size, case)
-    h = 1.0 / size
     oracle.lib()
-    t0 = time.perf_counter()
-    taken = len(oracle.run(U, (h, h, h), 1.4, 0.5, oracle.PERIODIC, steps))
-    el = time.perf_counter() - t0
-    return {"value": size ** 3 * taken / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+    every = oracle.threads()
+
+    def rate(n, nsteps):
+        U = make_input(n, case)
+        h = 1.0 / n
+        t0 = time.perf_counter()
+        taken = len(oracle.run(U, (h, h, h), 1.4, 0.5, oracle.PERIODIC, nsteps))
+        return n ** 3 * taken / (time.perf_counter() - t0), taken, time.perf_counter() - t0
+
+    value, taken, el = rate(size, steps)
+    by_threads = {str(every): round(value)}
+    for nt in sorted({max(every // 8, 1), 1}, reverse=True):
+        oracle.set_threads(nt)
+        by_threads[str(nt)] = round(rate(128, 2)[0])
+    oracle.set_threads(every)
+    return {"value": value, "unit": "cell-updates/s", "cores": every,
             "kind": "oracle",
             "sample": f"{case} case on a {size}^3 periodic mesh, {taken} RK2 step(s) incl. dt, "
-                      f"{el:.1f} s wall"}
+                      f"{el:.1f} s wall",
+            "by_threads": by_threads,
+            "by_threads_sample": f"{case} case on a 128^3 periodic mesh, 2 RK2 steps"}
 
 
-def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z):
+def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_steps=0):
     """Warm-up and timed gs_fluid_advance runs of one form from U0; returns
-    the figures and the dt of every step (warm-up first)."""
+    the figures and the dt of every step (warm-up first).  repeats > 1 times
+    that many blocks of `steps` steps in all (the first is the reported
+    one); host_steps > 0 then also times that many host-dt steps."""
     import torch
     from paper_1812_07977_amd import Fluid
     F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic", dtype=dtype)
@@ -130,9 +151,52 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z):
     per_kernel = {k: F.kernel_ms(k) for k in range(3)}
     t_sim = F.time
     result = F.to_f64(S) if dtype == "f64" else None
-    F.close()
     dts = torch.cat([log_w[:warmup], log_t[:steps]]).cpu().numpy()
-    return {"total_ms": total_ms, "per_kernel": per_kernel, "t_sim": t_sim}, dts, result
+    extra = {}
+    if repeats > 1:
+        # further timed blocks of the same length, continuing the run
+        reps = [total_ms]
+        for _ in range(repeats - 1):
+            torch.cuda.synchronize()
+            t0.record(stream)
+            F.advance(S, steps)
+            t1.record(stream)
+            F.sync()
+            reps.append(t0.elapsed_time(t1))
+        extra["repeat_ms"] = reps
+    if host_steps:
+        # the host-synchronised path: a reduction and a read-back of dt
+        # before every step
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(host_steps):
+            F.step(S, F.dt(S))
+        t1.record(stream)
+        F.sync()
+        extra["host_dt_ms"] = t0.elapsed_time(t1)
+        extra["host_steps"] = host_steps
+    F.profile(False)
+    F.close()
+    return {"total_ms": total_ms, "per_kernel": per_kernel, "t_sim": t_sim, **extra}, dts, result
+
+
+def copy_ceiling_gbs(mib=2048, reps=3):
+    """Measured HBM ceiling: the best of `reps` device-to-device copies of
+    mib MiB (read and write bytes over the event-timed duration)."""
+    import torch
+    a = torch.ones(mib * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 0.0
+    for _ in range(reps + 1):      # the first copy is a warm-up
+        torch.cuda.synchronize()
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del a, b
+    return best
 
 
 def roofline(dtype, n, case, per_kernel):
@@ -425,13 +489,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    r64, dts64, U64 = timed_run(U0, n, "f64", args.steps, args.warmup, args.tile_y, args.chunk_z)
+    r64, dts64, U64 = timed_run(U0, n, "f64", args.steps, args.warmup, args.tile_y, args.chunk_z,
+                                repeats=5, host_steps=20)
+    copy_gbs = copy_ceiling_gbs()
 
     cells = n ** 3
     ms_per_step = r64["total_ms"] / args.steps
     rate = cells * args.steps / (r64["total_ms"] / 1e3)
     alg_bytes_step = 200.0 * cells + 40.0 * cells / args.steps
     roof, alu = roofline("f64", n, args.case, r64["per_kernel"])
+    roof["frac_of_copy_ceiling"] = round(roof["achieved"] / copy_gbs, 4)
 
     line = {
         "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1,
@@ -445,6 +512,15 @@ def main():
         "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
                               for k, v in r64["per_kernel"].items()},
         "sim_time": r64["t_sim"],
+        "repeats": {"blocks": len(r64["repeat_ms"]), "steps_each": args.steps,
+                    "cell_updates_per_s": [round(cells * args.steps / (t / 1e3)) for t in r64["repeat_ms"]],
+                    "median": round(cells * args.steps / (sorted(r64["repeat_ms"])[len(r64["repeat_ms"]) // 2] / 1e3))},
+        "host_dt": {"value": cells * r64["host_steps"] / (r64["host_dt_ms"] / 1e3),
+                    "unit": "cell-updates/s", "steps": r64["host_steps"],
+                    "ms_per_step": r64["host_dt_ms"] / r64["host_steps"],
+                    "note": "gs_fluid_dt (reduction + 8-byte read-back + sync) then gs_fluid_step, "
+                            "240 B/cell-update"},
+        "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
         "roofline": roof,
         "alu": alu,
         "context": "paper: ~12X wall-time speedup of one V100 over 7 Power9 cores "

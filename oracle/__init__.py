@@ -50,6 +50,8 @@ def lib():
         L.ora_fill_ghosts.argtypes = [_I, _I, _I, _I, _P, _P]
         L.ora_fill_ghosts.restype = _I
         L.ora_threads.restype = _I
+        L.ora_set_threads.argtypes = [_I]
+        L.ora_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -168,3 +170,8 @@ def fill_ghosts(U, bc):
 
 def threads():
     return lib().ora_threads()
+
+
+def set_threads(n):
+    """Number of OpenMP threads for the mesh-level entry points."""
+    lib().ora_set_threads(int(n))

@@ -638,3 +638,13 @@ int ora_threads(void)
     return 1;
 #endif
 }
+
+/* Set that number (n >= 1); no effect without OpenMP. */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
