@@ -233,7 +233,7 @@ def test_profiling_counts_launches():
 # ---------------------------------------------------------------------------
 
 def test_full_256_sine_matches_oracle_everywhere():
-    n, steps = 256, 2
+    n, steps = 256, 10
     _say(f"case: sine {n}^3 periodic, {steps} steps, full comparison")
     U0 = wl.sine_wave(n, n, n)
     out, gdt, _ = gpu_run_device_dt(U0, "periodic", steps)
@@ -265,6 +265,19 @@ def test_full_512_sampled_windows_match_oracle(case):
         for f in range(5):
             s = scale[f] if scale[f] > 0 else np.max(scale)
             assert np.max(np.abs(g[f] - win[f])) / s <= TOL, (o, f)
+
+
+def test_full_512_three_steps_match_oracle_everywhere():
+    # the full per-GPU size, every cell (the oracle holds about 66 GB of
+    # ghosted arrays on the host)
+    n, steps = 512, 3
+    _say(f"case: plane0 {n}^3 periodic, {steps} steps, full comparison")
+    U0 = wl.random_plane(n, n, n, seed=0)
+    out, gdt, _ = gpu_run_device_dt(U0, "periodic", steps)
+    ref, odt = oracle_run(U0, "periodic", steps)
+    del U0
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
 
 
 def test_full_512_random_plane_conservation():
