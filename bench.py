@@ -152,7 +152,9 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
     total_ms = t0.elapsed_time(t1)
     per_kernel = {k: F.kernel_ms(k) for k in range(3)}
     t_sim = F.time
-    result = F.to_f64(S) if dtype == "f64" else None
+    # a copy: for FP64 the state itself is returned, and the blocks below
+    # advance it further
+    result = F.to_f64(S).clone() if dtype == "f64" else None
     dts = torch.cat([log_w[:warmup], log_t[:steps]]).cpu().numpy()
     extra = {}
     if repeats > 1:
