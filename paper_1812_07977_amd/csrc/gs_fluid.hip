@@ -106,10 +106,12 @@ __device__ __forceinline__ void load5(const T* __restrict__ base, long long fiel
     for (int f = 0; f < NV; ++f) u[f] = base[f * field + off];
 }
 
-// Streams that a substep reads or writes exactly once (U(n) and its
-// compensation in the combine, the outputs) carry the non-temporal hint, so
-// that they do not push the stage input, whose lines neighbouring tiles share
-// as halo, out of L2 (measured 3-4% faster second substeps at 512^3).
+// On large meshes the streams that a substep reads or writes exactly once
+// (U(n) and its compensation in the combine, the outputs) carry the
+// non-temporal hint, so that they do not push the stage input, whose lines
+// neighbouring tiles share as halo, out of the caches: measured 2-5% faster
+// steps from 192^3 up, 5-10% slower at 128^3 and below, where the state
+// stays in the 256 MB last-level cache between the substeps.
 template <typename T>
 __device__ __forceinline__ void load5_nt(const T* __restrict__ base, long long field, int off, T u[NV])
 {
@@ -151,7 +153,7 @@ __device__ __forceinline__ const Phys& phys64(const PhysT<float>&, const Phys& k
 // chunk kc of mesh g, time step dt.  Sets bad if a non-physical cell was
 // read and raises rmax to the largest signal rate written (RATE).  All
 // threads of the workgroup call it together (it synchronises on LDS).
-template <typename T, int TX, int TY, int STAGE, bool RATE>
+template <typename T, int TX, int TY, int STAGE, bool RATE, bool NTH>
 __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn,
                                            T* D0, const Geom& g, const PhysT<T>& kt, const Phys& K,
                                            int tix, int tiy, int kc, double dt, bool& bad,
@@ -343,10 +345,18 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         T Uk3[NV], Uo[NV], Co[NV], Do[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
         if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
-        if (STAGE == 2) load5_nt(Un + (long long)z * g.plane, F, own, Uo);
+        if (STAGE == 2) {
+            if (NTH) load5_nt(Un + (long long)z * g.plane, F, own, Uo);
+            else load5(Un + (long long)z * g.plane, F, own, Uo);
+        }
         if (KAHAN) {
-            load5_nt(Cn + (long long)z * g.plane, F, own, Co);
-            load5_nt(D0 + (long long)z * g.plane, F, own, Do);
+            if (NTH) {
+                load5_nt(Cn + (long long)z * g.plane, F, own, Co);
+                load5_nt(D0 + (long long)z * g.plane, F, own, Do);
+            } else {
+                load5(Cn + (long long)z * g.plane, F, own, Co);
+                load5(D0 + (long long)z * g.plane, F, own, Do);
+            }
         }
 
         // z-face above the own cell, from the register queue
@@ -392,11 +402,17 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
             if (active) {
                 T* po = Uout + (long long)z * g.plane + own;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(out[v], po + v * F);
+                for (int v = 0; v < NV; ++v) {
+                    if (NTH) __builtin_nontemporal_store(out[v], po + v * F);
+                    else po[v * F] = out[v];
+                }
                 if (KAHAN || KEEPD) {
                     T* pa = (KAHAN ? Cn : D0) + (long long)z * g.plane + own;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(aux[v], pa + v * F);
+                    for (int v = 0; v < NV; ++v) {
+                        if (NTH) __builtin_nontemporal_store(aux[v], pa + v * F);
+                        else pa[v * F] = aux[v];
+                    }
                 }
             }
             if (RATE && active) {
@@ -421,7 +437,7 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
 
 }
 
-template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE>
+template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE, bool NTH>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T>::waves)))
 stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom g, PhysT<T> kt,
              Phys kd, DevState* __restrict__ st, int parity, double dt_host, double t_end,
@@ -450,7 +466,8 @@ stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom
 
     bool bad = false;
     double rmax = 0.0;
-    stage_tile<T, TX, TY, STAGE, RATE>(Uin, Un, Uout, Cn, D0, g, kt, K, tix, tiy, kc, dt, bad, rmax);
+    stage_tile<T, TX, TY, STAGE, RATE, NTH>(Uin, Un, Uout, Cn, D0, g, kt, K, tix, tiy, kc, dt, bad,
+                                            rmax);
 
     // epilogue: flags and the max signal rate, one atomic per wavefront
     if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
@@ -535,9 +552,11 @@ batch_stage_kernel(const BatchInst* __restrict__ insts, int count, int total, in
         bool bad = false;
         double rmax = 0.0;
         if (STAGE == 1)
-            stage_tile<T, TX, TY, 1, false>(U, U, U1, nullptr, D0, g, kt, K, tix, tiy, kc, dt, bad, rmax);
+            stage_tile<T, TX, TY, 1, false, false>(U, U, U1, nullptr, D0, g, kt, K, tix, tiy, kc, dt,
+                                                   bad, rmax);
         else
-            stage_tile<T, TX, TY, 2, RATE>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad, rmax);
+            stage_tile<T, TX, TY, 2, RATE, false>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad,
+                                                  rmax);
         if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
         if (RATE) {
             for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
@@ -862,9 +881,20 @@ hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, b
     const PhysT<T> kt = phys_t<T>(h);
     const Phys kd = make_phys(h);
     dim3 grid(L.blocks), block(TX * TY);
-#define GS_LAUNCH(S_, D_, R_)                                                                    \
-    hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_>), grid, block, 0, h->stream, Uin, Un, \
-                       Uout, C, D, L.g, kt, kd, h->st, h->parity, dt_host, t_end, dt_log, step)
+    // non-temporal hints on meshes whose state does not stay in the
+    // last-level cache between the substeps
+    const bool nth = (double)NV * L.g.field * sizeof(T) >= 128.0 * 1024 * 1024;
+#define GS_LAUNCH(S_, D_, R_)                                                                     \
+    do {                                                                                          \
+        if (nth)                                                                                  \
+            hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_, true>), grid, block, 0,       \
+                               h->stream, Uin, Un, Uout, C, D, L.g, kt, kd, h->st, h->parity,     \
+                               dt_host, t_end, dt_log, step);                                     \
+        else                                                                                      \
+            hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_, false>), grid, block, 0,      \
+                               h->stream, Uin, Un, Uout, C, D, L.g, kt, kd, h->st, h->parity,     \
+                               dt_host, t_end, dt_log, step);                                     \
+    } while (0)
     if (stage == 1) {
         if (devdt) GS_LAUNCH(1, true, false);
         else GS_LAUNCH(1, false, false);
