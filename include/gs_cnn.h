@@ -51,7 +51,8 @@ int gs_cnn_param_count(void);
  * ratio of specific heats gamma (for the positivity check of a corrected
  * state), on the current device and the given stream.  Allocates the
  * activations, gradients and optimizer state for that mesh (about 1 KB per
- * cell); parameters start at zero until gs_cnn_set_params.
+ * cell, plus 57 MB of weight-gradient partial sums); parameters start at
+ * zero until gs_cnn_set_params.
  */
 int gs_cnn_create(int nx, int ny, int nz, int bc, double gamma, void* stream, gs_cnn** out);
 

@@ -28,9 +28,11 @@
 // gradient of a convolution on a periodic mesh is the convolution of the
 // output gradient with mirrored taps and transposed channels, so the same
 // kernel runs the backward pass, with the ReLU mask fused into its epilogue.
-// The weight gradient is a GEMM over cells (K = cells): M = input channels,
-// N = output channels, per tap; partial sums per wave, reduced in a fixed
-// order by a second kernel.
+// Its input tile and halo are staged in LDS once per plane.  The weight
+// gradient is a GEMM over cells (K = cells): M = input channels, N = output
+// channels, for all 27 taps per workgroup over its share of the mesh rows;
+// one partial sum per workgroup and tap, reduced in a fixed order by a
+// second kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
