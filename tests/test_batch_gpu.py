@@ -170,3 +170,37 @@ def test_full_batch_of_64_matches_problems_alone(dtype):
         ref, t = _alone(probs[i], dtype, "periodic", 2, (ty, kz))
         assert np.array_equal(got[i], ref), i
         assert times[i] == t, i
+
+
+@pytest.mark.parametrize("dtype,bc", [("f64", "outflow"), ("f64", "periodic"), ("f32", "outflow")])
+def test_degenerate_meshes_in_a_batch(dtype, bc):
+    # one-cell-thick and tiny meshes beside a ragged one: every work item
+    # maps its ghost columns and planes to valid cells
+    from paper_1812_07977_amd.batch import Batch
+    dims = [(1, 1, 7), (2, 2, 2), (64, 1, 1), (5, 33, 17), (1, 9, 1)]
+    probs = _problems(dims, seed0=800)
+    _say(f"case: degenerate batch {dims} {dtype} {bc}, 4 steps")
+    states = [_state(U0, dtype, bc) for U0 in probs]
+    with Batch(dims, states, bc=bc, dtype=dtype) as B:
+        B.advance(4)
+        times = B.times()
+        got = [to_cpu(S) for S in states]
+    for i, U0 in enumerate(probs):
+        ref, t = _alone(U0, dtype, bc, 4, (0, 0))
+        assert np.array_equal(got[i], ref), i
+        assert times[i] == t, i
+
+
+def test_batch_of_one_matches_the_oracle():
+    from paper_1812_07977_amd.batch import Batch
+    dims = [(40, 24, 20)]
+    probs = _problems(dims, seed0=900)
+    _say("case: batch of one 40x24x20 outflow, 10 steps")
+    states = [to_gpu(probs[0])]
+    with Batch(dims, states, bc="outflow") as B:
+        B.advance(10)
+        times = B.times()
+        got = to_cpu(states[0])
+    ref, dts = oracle_run(probs[0], "outflow", 10)
+    assert max(rel_linf(got, ref)) <= 1e-12
+    assert abs(times[0] - float(np.sum(dts))) <= 1e-14 * 10 * float(np.sum(dts))
