@@ -500,22 +500,52 @@ __device__ __forceinline__ const PhysT<float>& batch_phys(const BatchInst& I, co
     return I.kf;
 }
 
+// Work-item dispenser of the batched launches: one counter per XCD share of
+// the items and a count of finished workgroups, each in its own 128-byte
+// line.  The last workgroup of a launch to finish zeroes them all, so every
+// launch starts from zero without a memset (graph replays included).
+constexpr int SCHED_STRIDE = 32;
+constexpr int SCHED_WORDS = 9 * SCHED_STRIDE;
+
 // Substep STAGE of every problem of a batch with its own device time step.
 // Persistent: a grid sized to the resident workgroups walks the work items
-// (all tiles and z-chunks of all problems, problem by problem); workgroup b
-// runs on XCD b % 8 and takes items from that XCD's contiguous share, so
-// neighbouring tiles of a problem meet in one L2.  Each item is exactly the
-// work of one workgroup of stage_kernel, so a problem advanced in a batch
-// and alone with the same tile shape and chunk give bit-identical results.
+// (all tiles and z-chunks of all problems, problem by problem).  Items are
+// split into eight contiguous shares, one per XCD; workgroup b runs on XCD
+// b % 8 and draws the next item of its XCD's share from that share's
+// counter, so neighbouring tiles of a problem meet in one L2 and cheap and
+// dear items (ragged tiles, short last chunks) even out over the
+// workgroups.  Once its own share is drawn out it draws from the other
+// XCDs' shares in turn.  Each item is exactly the work of one workgroup of
+// stage_kernel, whichever workgroup runs it, so a problem advanced in a
+// batch and alone with the same tile shape and chunk give bit-identical
+// results.
 template <typename T, int TX, int TY, int STAGE, bool RATE>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T>::waves)))
 batch_stage_kernel(const BatchInst* __restrict__ insts, int count, int total, int parity,
-                   double t_end)
+                   double t_end, unsigned int* __restrict__ sched)
 {
+    __shared__ int s_item;
     const int tid = threadIdx.x;
-    const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3, nw = gridDim.x >> 3;
-    const int beg = (int)((long long)total * xcd / 8), end = (int)((long long)total * (xcd + 1) / 8);
-    for (int item = beg + w; item < end; item += nw) {
+    const int xcd = blockIdx.x & 7;
+    int tried = 0;  // shares found empty so far (thread 0 only)
+    for (;;) {
+        if (tid == 0) {
+            int next = -1;
+            while (tried < 8) {
+                const int s = (xcd + tried) & 7;
+                const long long beg = (long long)total * s / 8, end = (long long)total * (s + 1) / 8;
+                const unsigned int k = atomicAdd(&sched[s * SCHED_STRIDE], 1u);
+                if (beg + k < end) {
+                    next = (int)(beg + k);
+                    break;
+                }
+                ++tried;
+            }
+            s_item = next;
+        }
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // the same in every lane
+        if (item < 0) break;
         int lo = 0, hi = count - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -563,8 +593,22 @@ batch_stage_kernel(const BatchInst* __restrict__ insts, int count, int total, in
             if ((tid & 63) == 0)
                 atomicMax(&st->rate[parity ^ 1], (unsigned long long)__double_as_longlong(rmax));
         }
-        __syncthreads();  // the next item reuses the LDS
+        __syncthreads();  // the next item reuses the LDS and s_item
     }
+    // Every draw of this workgroup has returned before its finish is
+    // counted; the last to finish has seen every other's, so no draw of this
+    // launch is still in flight when it zeroes the words.
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&sched[8 * SCHED_STRIDE], 1u) == gridDim.x - 1) {
+            for (int s = 0; s < 9; ++s) atomicExch(&sched[s * SCHED_STRIDE], 0u);
+        }
+    }
+}
+
+__global__ void clear_words_kernel(unsigned int* __restrict__ w, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
 }
 
 // Max signal rate over all cells of U (first pass: one partial per block) and
@@ -1326,6 +1370,7 @@ struct gs_batch {
     double* partial;            // reduction partials, RED_BLOCKS per problem
     BatchInst* insts_dev;       // device table for the live states
     BatchInst* tune_dev;        // device table for scratch states
+    unsigned int* sched;        // work-item dispenser (SCHED_WORDS words)
     int total_items;
     int tile_y, chunk_z;
     int grid[2];                // persistent grid of substep 1 and 2
@@ -1427,9 +1472,9 @@ template <typename T, int TX, int TY>
 hipError_t batch_launch_t(gs_batch* h, const BatchInst* table, int total, int parity, double t_end)
 {
     hipLaunchKernelGGL((batch_stage_kernel<T, TX, TY, 1, false>), dim3(h->grid[0]), dim3(TX * TY), 0,
-                       h->stream, table, h->count, total, parity, t_end);
+                       h->stream, table, h->count, total, parity, t_end, h->sched);
     hipLaunchKernelGGL((batch_stage_kernel<T, TX, TY, 2, true>), dim3(h->grid[1]), dim3(TX * TY), 0,
-                       h->stream, table, h->count, total, parity, t_end);
+                       h->stream, table, h->count, total, parity, t_end, h->sched);
     return hipGetLastError();
 }
 
@@ -1625,6 +1670,7 @@ int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc
         (e = hipMalloc((void**)&h->partial, sizeof(double) * RED_BLOCKS * count)) != hipSuccess ||
         (e = hipMalloc((void**)&h->insts_dev, sizeof(BatchInst) * count)) != hipSuccess ||
         (e = hipMalloc((void**)&h->tune_dev, sizeof(BatchInst) * count)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->sched, sizeof(unsigned int) * SCHED_WORDS)) != hipSuccess ||
         (e = hipHostMalloc((void**)&h->host_st, sizeof(DevState) * count, hipHostMallocDefault)) !=
             hipSuccess ||
         (e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess ||
@@ -1638,6 +1684,7 @@ int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc
         hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st + i);
         hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h->stream, h->tune_st + i);
     }
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, h->stream, h->sched, SCHED_WORDS);
     if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         int r = bhip(nullptr, e, "batch init");
         gs_batch_destroy(h);
@@ -1828,6 +1875,7 @@ void gs_batch_destroy(gs_batch* h)
     if (h->partial) (void)hipFree(h->partial);
     if (h->insts_dev) (void)hipFree(h->insts_dev);
     if (h->tune_dev) (void)hipFree(h->tune_dev);
+    if (h->sched) (void)hipFree(h->sched);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);

@@ -80,7 +80,12 @@ def _dyadic_params(rng):
 @pytest.mark.parametrize("shape,bc", [((32, 16, 8), "periodic"), ((20, 12, 6), "outflow"),
                                       ((16, 16, 16), "periodic"),
                                       # 16 tiles and 160 planes: workgroups march 2 planes
-                                      ((64, 64, 160), "periodic")])
+                                      ((64, 64, 160), "periodic"),
+                                      # degenerate meshes: one cell, one row, one plane;
+                                      # every halo cell maps back into the mesh
+                                      ((1, 1, 1), "periodic"), ((1, 1, 1), "outflow"),
+                                      ((17, 1, 3), "outflow"), ((3, 2, 1), "periodic"),
+                                      ((1, 40, 2), "periodic")])
 def test_forward_is_bit_exact_on_exactly_representable_data(shape, bc):
     nx, ny, nz = shape
     _say(f"case: cnn forward dyadic {shape} {bc}")
@@ -92,7 +97,8 @@ def test_forward_is_bit_exact_on_exactly_representable_data(shape, bc):
         y = N.forward(_pair(head)).cpu().numpy().astype(np.float64)
     obc = ocnn.PERIODIC if bc == "periodic" else ocnn.OUTFLOW
     ref, (_, h1, _, h2) = _oracle_forward_bf16(head, _params_from_flat(flat), obc)
-    assert np.count_nonzero(h1) > 0.2 * h1.size and np.count_nonzero(h2) > 0.2 * h2.size
+    if nx * ny * nz >= 64:
+        assert np.count_nonzero(h1) > 0.2 * h1.size and np.count_nonzero(h2) > 0.2 * h2.size
     assert np.array_equal(y, ref)
 
 
@@ -133,11 +139,13 @@ def test_forward_random_weights_within_fp32_accumulation_bound():
     assert np.median(err / absum) < 1e-3
 
 
-@pytest.mark.parametrize("shape", [(32, 8, 8), (96, 8, 6)])
+@pytest.mark.parametrize("shape", [(32, 8, 8), (96, 8, 6), (32, 1, 1), (64, 3, 1)])
 def test_gradients_match_the_oracle(shape):
     # (96, 8, 6): three 32-cell blocks per row (the weight-gradient kernel
     # takes two per step, so the second of the last pair is masked) and
-    # fewer rows than workgroups (some sum nothing)
+    # fewer rows than workgroups (some sum nothing); (32, 1, 1) and
+    # (64, 3, 1): one row or one plane, where every y or z shift wraps onto
+    # the cell itself
     nx, ny, nz = shape
     _say(f"case: cnn gradients {nx}x{ny}x{nz} periodic")
     from paper_1812_07977_amd.learned import split_params
