@@ -56,8 +56,8 @@ KERNEL_NAMES = {0: "stage_kernel<1> (substep 1)", 1: "stage_kernel<2> (substep 2
                 2: "rate reduction"}
 METRIC = "cell-updates/s per RK2 step & HBM GB/s; plain FP64 vs chosen forms @ L1 err"
 # the stage kernels' source and the build script that sets their flags
-KERNEL_SOURCES = ["paper_1812_07977_amd/csrc/gs_fluid.hip", "paper_1812_07977_amd/csrc/euler_math.hpp",
-                  "paper_1812_07977_amd/build.py"]
+KERNEL_SOURCES = ["paper_1812_07977_amd/csrc/gs_fluid.hip", "paper_1812_07977_amd/csrc/stage.hpp",
+                  "paper_1812_07977_amd/csrc/euler_math.hpp", "paper_1812_07977_amd/build.py"]
 
 
 def source_hash():

@@ -2,15 +2,17 @@
 
     python -m paper_1812_07977_amd.build
 
-Compiles csrc/gs_fluid.hip (the Euler step) and csrc/gs_cnn.hip (the
-learned-correction network) with hipcc for gfx950 only, each to an object
-with its own flags, and links them into one library.  Floating-point
-contraction is off (the kernels write every fused multiply-add explicitly)
-and packed FP32 instructions are disabled.  The Euler step is scheduled with
-the compiler's iterative ILP strategy, which keeps the FP64 stage kernels at
-three waves per SIMD and measured 3-5% faster than the default scheduler for
-them; the network's kernels order their own loads and products and keep the
-default.
+Compiles csrc/gs_fluid.hip (the Euler step), csrc/gs_batch.hip (its
+batched form) and csrc/gs_cnn.hip (the learned-correction network) with
+hipcc for gfx950 only, each to an object with its own flags, and links them
+into one library.  Floating-point contraction is off (the kernels write
+every fused multiply-add explicitly) and packed FP32 instructions are
+disabled.  The single-problem Euler step is scheduled with the compiler's
+iterative ILP strategy, which keeps the FP64 stage kernels at three waves
+per SIMD and measured 3-5% faster than the default scheduler for them; the
+batched kernels keep the default, under which their item loop fits three
+waves too; the network's kernels order their own loads and products and
+keep the default.
 """
 import os
 import subprocess
@@ -32,6 +34,7 @@ FLAGS = [
 # sources and their own flags
 SRCS = {
     os.path.join(HERE, "csrc", "gs_fluid.hip"): ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    os.path.join(HERE, "csrc", "gs_batch.hip"): [],
     os.path.join(HERE, "csrc", "gs_cnn.hip"): [],
 }
 

@@ -1,0 +1,489 @@
+// stage.hpp -- device code shared by the single-problem path (gs_fluid.hip)
+// and the batched form (gs_batch.hip): mesh geometry and tiling, the device
+// words of a problem, the fused substep body of one (tile, z-chunk) item, and
+// the reduction and small state kernels.  The two sources are compiled with
+// their own scheduling flags; each gets its own copy of these kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "euler_math.hpp"
+#include "gs_fluid.h"
+
+namespace gs {
+
+// Mesh geometry and tiling, passed by value.
+struct Geom {
+    int nx, ny, nz;
+    int periodic;
+    int plane;          // nx * ny
+    long long field;    // nx * ny * nz: distance between fields
+    int ntx, nty;       // tiles along x, y
+    int kz, nchunk;     // planes per chunk, chunks along z
+    int band;           // tiles per XCD band (0: plain block order)
+};
+
+// Device-resident words of a handle.  rate[] and t[] are ping-pong pairs
+// indexed by the step parity: step s reads slot s&1 and prepares slot
+// (s+1)&1, so no kernel ever reads a word another kernel of the same step
+// writes.  rate holds the IEEE bits of a non-negative double, so an unsigned
+// max is a floating-point max.
+struct DevState {
+    unsigned long long rate[2];
+    double t[2];
+    unsigned long long rate_dt;  // result slot of the dt reduction
+    unsigned int flags;          // bit 0: a non-physical cell was read
+    unsigned int pad;
+    double tot[NV];              // conserved totals of the last totals pass
+};
+
+__device__ __forceinline__ int map_index(int i, int n, int periodic)
+{
+    if (periodic) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Workgroup -> (tile x, tile y, chunk).  Workgroups are dispatched to the 8
+// XCDs round-robin; with band > 0 the n-th workgroup an XCD receives works on
+// chunk n / band of that XCD's band of tiles, so at any moment the XCDs hold
+// adjacent bands of the same z-chunk.
+__device__ __forceinline__ void block_tile(const Geom& g, int& tx0, int& ty0, int& kc)
+{
+    int b = blockIdx.x;
+    int tile, chunk;
+    if (g.band > 0) {
+        int xcd = b & 7, n = b >> 3;
+        chunk = n / g.band;
+        tile = xcd * g.band + (n - chunk * g.band);
+    } else {
+        int ntile = g.ntx * g.nty;
+        chunk = b / ntile;
+        tile = b - chunk * ntile;
+    }
+    int ty = tile / g.ntx;
+    tx0 = tile - ty * g.ntx;
+    ty0 = ty;
+    kc = chunk;
+}
+
+template <typename T>
+__device__ __forceinline__ void load5(const T* __restrict__ base, long long field, int off, T u[NV])
+{
+#pragma unroll
+    for (int f = 0; f < NV; ++f) u[f] = base[f * field + off];
+}
+
+// On large meshes the streams that a substep reads or writes exactly once
+// (U(n) and its compensation in the combine, the outputs) carry the
+// non-temporal hint, so that they do not push the stage input, whose lines
+// neighbouring tiles share as halo, out of the caches: measured 2-5% faster
+// steps from 192^3 up, 5-10% slower at 128^3 and below, where the state
+// stays in the 256 MB last-level cache between the substeps.
+template <typename T>
+__device__ __forceinline__ void load5_nt(const T* __restrict__ base, long long field, int off, T u[NV])
+{
+#pragma unroll
+    for (int f = 0; f < NV; ++f) u[f] = __builtin_nontemporal_load(base + f * field + off);
+}
+
+// Fused RK2 substep on states of type T (double: the FP64 form; float: the
+// FP32 form).  STAGE 1: Uout = Uin + dU(Uin); the FP32 form also stores the
+// increment dU(Uin) itself into D0.  STAGE 2, FP64: Uout = 0.5 ((Un + Uin) +
+// dU(Uin)); FP32: the same value written as U(n) plus the increment
+// 0.5 (D0 + dU(Uin)), summed with Kahan compensation, Cn holding the
+// compensation of Un (read and rewritten).  Storing D0 keeps the first
+// substep's increment exact: U(1) - U(n) would have lost whatever part of it
+// falls below the rounding of U(1).  Uout may alias Un (each cell's Un and Cn
+// are read only by the thread that writes them).  DEVDT:
+// dt = cfl / max rate (slot parity), clipped to t_end; else dt = dt_host.
+// RATE: accumulate the max signal rate of Uout into rate[parity ^ 1].
+// Primitive recovery and signal rates run in FP64 for both forms (kd); the
+// reconstruction and flux arithmetic runs in T (kt).
+#ifndef GS_STAGE_WAVES_PER_EU
+#define GS_STAGE_WAVES_PER_EU 2
+#endif
+#ifndef GS_STAGE_WAVES_PER_EU_F32
+#define GS_STAGE_WAVES_PER_EU_F32 3
+#endif
+
+template <typename T>
+struct StageOcc {
+    static constexpr int waves = sizeof(T) == 8 ? GS_STAGE_WAVES_PER_EU : GS_STAGE_WAVES_PER_EU_F32;
+};
+
+// FP64 constants for the FP64 parts: the FP64 form's own constants, or the
+// separate FP64 set of the FP32 form.
+__device__ __forceinline__ const Phys& phys64(const Phys& kt, const Phys&) { return kt; }
+__device__ __forceinline__ const Phys& phys64(const PhysT<float>&, const Phys& kd) { return kd; }
+
+// The work of one (tile, z-chunk) item of a substep: tile (tix, tiy),
+// chunk kc of mesh g, time step dt.  Sets bad if a non-physical cell was
+// read and raises rmax to the largest signal rate written (RATE).  All
+// threads of the workgroup call it together (it synchronises on LDS); tid
+// is the caller's thread index in the workgroup.
+template <typename T, int TX, int TY, int STAGE, bool RATE, bool NTH>
+__device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn,
+                                           T* D0, const Geom& g, const PhysT<T>& kt, const Phys& K,
+                                           int tix, int tiy, int kc, double dt, bool& bad,
+                                           double& rmax, int tid)
+{
+    constexpr int NT = TX * TY;
+    constexpr int WX = TX + 4, WY = TY + 4;
+    constexpr bool KAHAN = (STAGE == 2) && (sizeof(T) == 4);   // FP32 stage 2
+    constexpr bool KEEPD = (STAGE == 1) && (sizeof(T) == 4);   // FP32 stage 1
+    static_assert(4 * (TX + TY) <= NT, "one halo cell per thread at most");
+    static_assert(TX + TY <= NT, "one edge face per thread at most");
+    __shared__ T Ws[NV][WY][WX];     // primitives of the plane, +2 halo
+    __shared__ T Fx[NV][TY][TX + 1]; // x-face fluxes, face i-1/2 at [i]
+    __shared__ T Fy[NV][TY + 1][TX]; // y-face fluxes, face j-1/2 at [j]
+    constexpr int NH = 4 * (TX + TY);     // halo cells of one plane
+    __shared__ T Hr[3][NV][NH];      // halo ring: raw states of 3 planes
+
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int z0 = kc * g.kz;
+    const int z1 = min(z0 + g.kz, g.nz);
+
+    // own column (ghost columns of ragged tiles map to valid cells)
+    const int i = x0 + tx, j = y0 + ty;
+    const bool active = (i < g.nx) & (j < g.ny);
+    const int own = map_index(j, g.ny, g.periodic) * g.nx + map_index(i, g.nx, g.periodic);
+
+    // halo role: 4 cells per tile row (x) and per tile column (y).  Halo
+    // thread h loads its cell of plane z+3 in the iteration of plane z, at
+    // the same time as the neighbouring tiles load that plane as their own
+    // columns, so the shared cache lines are fetched from HBM once; the raw
+    // values wait in the thread's own slots of the LDS ring Hr until the
+    // plane is staged (no other thread touches those slots).
+    int hxl = 0, hyl = 0, hoff = 0;
+    bool halo = false;
+    if (tid < 4 * TY) {
+        int q = tid & 3;
+        hyl = tid >> 2;
+        hxl = q < 2 ? q - 2 : TX + q - 2;
+        halo = true;
+    } else if (tid < 4 * TY + 4 * TX) {
+        int h = tid - 4 * TY;
+        int q = h / TX;
+        hxl = h - q * TX;
+        hyl = q < 2 ? q - 2 : TY + q - 2;
+        halo = true;
+    }
+    if (halo)
+        hoff = map_index(y0 + hyl, g.ny, g.periodic) * g.nx + map_index(x0 + hxl, g.nx, g.periodic);
+
+    // edge-face role: the last TX + TY threads compute the faces on the far
+    // edges of the tile, y-faces above row TY-1 (e < TX) and x-faces right of
+    // column TX-1.  Both are evaluated as y-faces: for an x-face the two
+    // tangential velocity components are exchanged through the LDS addressing
+    // (and exchanged back on the way out); hll_flux orders its one
+    // cross-component sum so that this performs the very operations of an
+    // x-face evaluation, giving bit-identical fluxes.
+    const int e = tid - (NT - (TX + TY));
+    constexpr int PLW = WY * WX;               // one field of Ws
+    constexpr int PFX = TY * (TX + 1), PFY = (TY + 1) * TX;
+    int e_base = 0, e_step = 0, e_v1 = PLW, e_v2 = 2 * PLW;
+    T* e_out = nullptr;
+    int e_f1 = PFY, e_f2 = 2 * PFY, e_fs = PFY;
+    if (e >= 0 && e < TX) {
+        e_base = TY * WX + e + 2;
+        e_step = WX;
+        e_out = &Fy[0][TY][e];
+    } else if (e >= TX) {
+        const int r = e - TX;
+        e_base = (r + 2) * WX + TX;
+        e_step = 1;
+        e_v1 = 2 * PLW;
+        e_v2 = PLW;
+        e_out = &Fx[0][r][TX];
+        e_f1 = 2 * PFX;
+        e_f2 = PFX;
+        e_fs = PFX;
+    }
+
+    const T dtT = (T)dt;
+
+    const long long F = g.field;
+    auto plane_ptr = [&](const T* base, int z) {
+        return base + (long long)map_index(z, g.nz, g.periodic) * g.plane;
+    };
+
+    // ---- prologue: planes z0-2 .. z0+2 of the own column, halo of z0 ----
+    T Uk[NV], Uk1[NV], Uk2[NV], Hk[NV];
+    const int hslot = halo ? tid : 0;
+    T Wk[NV], Wk1[NV], WLz[NV], Fm[NV];
+    {
+        T Um2[NV], Um1[NV], Wm2[NV], Wm1[NV];
+        load5(plane_ptr(Uin, z0 - 2), F, own, Um2);
+        load5(plane_ptr(Uin, z0 - 1), F, own, Um1);
+        load5(plane_ptr(Uin, z0), F, own, Uk);
+        load5(plane_ptr(Uin, z0 + 1), F, own, Uk1);
+        load5(plane_ptr(Uin, z0 + 2), F, own, Uk2);
+        if (halo) {
+            // ring: planes z0, z0+1 stored, z0+2 held in registers
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                T h[NV];
+                load5(plane_ptr(Uin, z0 + q), F, hoff, h);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Hr[(z0 + q) % 3][v][hslot] = h[v];
+            }
+            load5(plane_ptr(Uin, z0 + 2), F, hoff, Hk);
+        }
+        bad |= !cons_to_prim(Um2, Wm2, K);
+        bad |= !cons_to_prim(Um1, Wm1, K);
+        bad |= !cons_to_prim(Uk, Wk, K);
+        bad |= !cons_to_prim(Uk1, Wk1, K);
+        face_flux<2>(Wm2, Wm1, Wk, Wk1, kt, Fm);  // face z0 - 1/2
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            WLz[v] = fmaR(T(0.5), minmod(Wk[v] - Wm1[v], Wk1[v] - Wk[v]), Wk[v]);
+    }
+
+
+    for (int z = z0; z < z1; ++z) {
+        // stage the plane's primitives in LDS
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ws[v][ty + 2][tx + 2] = Wk[v];
+        if (halo) {
+            T w[NV];
+            T h[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Hr[(z + 2) % 3][v][hslot] = Hk[v];   // plane z+2, loaded last iteration
+                h[v] = Hr[z % 3][v][hslot];           // plane z
+            }
+            cons_to_prim(h, w, K);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ws[v][hyl + 2][hxl + 2] = w[v];
+        }
+        __syncthreads();
+
+        // in-plane faces: x-face left of the own cell, y-face below it
+        {
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a[v] = Ws[v][ty + 2][tx];
+                b[v] = Ws[v][ty + 2][tx + 1];
+                c[v] = Ws[v][ty + 2][tx + 2];
+                d[v] = Ws[v][ty + 2][tx + 3];
+            }
+            face_flux<0>(a, b, c, d, kt, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fx[v][ty][tx] = f[v];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                a[v] = Ws[v][ty][tx + 2];
+                b[v] = Ws[v][ty + 1][tx + 2];
+                d[v] = Ws[v][ty + 3][tx + 2];
+            }
+            face_flux<1>(a, b, c, d, kt, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fy[v][ty][tx] = f[v];
+        }
+        // faces on the far edges of the tile (one evaluation per lane)
+        if (e >= 0) {
+            const T* ws = &Ws[0][0][0];
+            const int off[NV] = {0, e_v1, e_v2, 3 * PLW, 4 * PLW};
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const T* p = ws + off[v] + e_base;
+                a[v] = p[0];
+                b[v] = p[e_step];
+                c[v] = p[2 * e_step];
+                d[v] = p[3 * e_step];
+            }
+            face_flux<1>(a, b, c, d, kt, f);
+            e_out[0] = f[0];
+            e_out[e_f1] = f[1];
+            e_out[e_f2] = f[2];
+            e_out[3 * e_fs] = f[3];
+            e_out[4 * e_fs] = f[4];
+        }
+        __syncthreads();
+
+        // prefetch plane z+3 of the own column and of the halo; in stage 2
+        // load U(n) (FP32: with its compensation and the first increment)
+        // of this plane for the combine below.  Loading these one plane
+        // ahead instead would keep 10-15 more registers live and cost the
+        // FP64 second substep its third wave per SIMD.
+        T Uk3[NV], Uo[NV], Co[NV], Do[NV];
+        load5(plane_ptr(Uin, z + 3), F, own, Uk3);
+        if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
+        if (STAGE == 2) {
+            if (NTH) load5_nt(Un + (long long)z * g.plane, F, own, Uo);
+            else load5(Un + (long long)z * g.plane, F, own, Uo);
+        }
+        if (KAHAN) {
+            if (NTH) {
+                load5_nt(Cn + (long long)z * g.plane, F, own, Co);
+                load5_nt(D0 + (long long)z * g.plane, F, own, Do);
+            } else {
+                load5(Cn + (long long)z * g.plane, F, own, Co);
+                load5(D0 + (long long)z * g.plane, F, own, Do);
+            }
+        }
+
+        // z-face above the own cell, from the register queue
+        T Fp[NV], W2[NV];
+        {
+            T R[NV];
+            bad |= !cons_to_prim(Uk2, W2, K);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const T w0 = Ws[v][ty + 2][tx + 2];
+                T s1 = minmod(Wk1[v] - w0, W2[v] - Wk1[v]);
+                R[v] = fmaR(T(-0.5), s1, Wk1[v]);
+                Wk[v] = fmaR(T(0.5), s1, Wk1[v]);  // left state of face z+3/2
+            }
+            hll_flux<2>(WLz, R, kt, Fp);
+        }
+
+        // divergence, RK combine, store
+        {
+            T out[NV], aux[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T acc = (Fx[v][ty][tx + 1] - Fx[v][ty][tx]) * kt.inv_h[0];
+                acc = acc + (Fy[v][ty + 1][tx] - Fy[v][ty][tx]) * kt.inv_h[1];
+                acc = acc + (Fp[v] - Fm[v]) * kt.inv_h[2];
+                T du = -dtT * acc;
+                if (STAGE == 1) {
+                    out[v] = Uk[v] + du;
+                    aux[v] = du;
+                } else if (!KAHAN) {
+                    out[v] = T(0.5) * ((Uo[v] + Uk[v]) + du);
+                } else {
+                    // U(n+1) = U(n) + inc, inc = 0.5 (dU(U(n)) + dU(U(1))),
+                    // summed with Kahan compensation: the represented value
+                    // is head - compensation
+                    T inc = T(0.5) * (Do[v] + du);
+                    T y = inc - Co[v];
+                    T s = Uo[v] + y;
+                    aux[v] = (s - Uo[v]) - y;
+                    out[v] = s;
+                }
+            }
+            if (active) {
+                T* po = Uout + (long long)z * g.plane + own;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (NTH) __builtin_nontemporal_store(out[v], po + v * F);
+                    else po[v * F] = out[v];
+                }
+                if (KAHAN || KEEPD) {
+                    T* pa = (KAHAN ? Cn : D0) + (long long)z * g.plane + own;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        if (NTH) __builtin_nontemporal_store(aux[v], pa + v * F);
+                        else pa[v * F] = aux[v];
+                    }
+                }
+            }
+            if (RATE && active) {
+                double r;
+                cell_rate(out, K, r);
+                rmax = __builtin_fmax(rmax, r);
+            }
+        }
+
+        // rotate the queue: Wk holds the new left z-face state until here
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            WLz[v] = Wk[v];
+            Wk[v] = Wk1[v];
+            Wk1[v] = W2[v];
+            Uk[v] = Uk1[v];
+            Uk1[v] = Uk2[v];
+            Uk2[v] = Uk3[v];
+            Fm[v] = Fp[v];
+        }
+    }
+
+}
+
+namespace {
+
+// Max signal rate over all cells of U (first pass: one partial per block) and
+// the non-physical flag.  For the FP32 form U is the head of the state.
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+rate_partial_kernel(const T* __restrict__ U, long long ncell, Phys k,
+                    double* __restrict__ partial, DevState* __restrict__ st)
+{
+    __shared__ double red[RED_THREADS / 64];
+    double rmax = 0.0;
+    bool bad = false;
+    for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * RED_THREADS) {
+        T u[NV];
+#pragma unroll
+        for (int f = 0; f < NV; ++f) u[f] = U[f * ncell + c];
+        double r;
+        bad |= !cell_rate(u, k, r);
+        rmax = __builtin_fmax(rmax, r);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->flags, 1u);
+    for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < RED_THREADS / 64; ++w) m = __builtin_fmax(m, red[w]);
+        partial[blockIdx.x] = m;
+    }
+}
+
+// Second pass: max of the partials into *dst (as IEEE bits).
+__global__ void __launch_bounds__(RED_THREADS)
+rate_final_kernel(const double* __restrict__ partial, int n, unsigned long long* dst)
+{
+    __shared__ double red[RED_THREADS / 64];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += RED_THREADS) m = __builtin_fmax(m, partial[i]);
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < RED_THREADS / 64; ++w) m = __builtin_fmax(m, red[w]);
+        m = __builtin_fmax(red[0], m);
+        *dst = (unsigned long long)__double_as_longlong(m);
+    }
+}
+
+// Small state writes, as kernels so that the host never records a memset.
+__global__ void init_state_kernel(DevState* st)
+{
+    st->rate[0] = st->rate[1] = 0ull;
+    st->t[0] = st->t[1] = 0.0;
+    st->rate_dt = 0ull;
+    st->flags = 0u;
+    st->pad = 0u;
+    for (int f = 0; f < NV; ++f) st->tot[f] = 0.0;
+}
+
+__global__ void clear_flags_kernel(DevState* st) { st->flags = 0u; }
+
+}  // namespace
+
+// Host-side sizes shared by both sources.
+inline size_t elem_size(int dtype) { return dtype == GS_F32 ? sizeof(float) : sizeof(double); }
+
+// Substep workspace: U(1); the FP32 form also keeps the first increment.
+inline long long state_work_bytes(long long ncell, int dtype)
+{
+    return ncell * NV * (long long)elem_size(dtype) * (dtype == GS_F32 ? 2 : 1);
+}
+
+}  // namespace gs
