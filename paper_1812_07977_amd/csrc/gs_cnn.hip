@@ -890,22 +890,33 @@ __device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
 }
 
 // the per-field quantity whose mean the correction removes: y (mode 0) or
-// S y (mode 1), S from the head of U
-__device__ __forceinline__ void scaled_output(const float* __restrict__ U, const float* __restrict__ y,
-                                              long long ncell, long long v, const Norm& nm,
-                                              double out[NF])
+// S y (mode 1), S from the head of U; from the cell's values of both
+__device__ __forceinline__ void scaled_from(const float head[NF], const float yv[NF], const Norm& nm,
+                                            double out[NF])
 {
     double S[NF] = {1.0, 1.0, 1.0, 1.0, 1.0};
     if (nm.mode == 1) {
         double u[NF];
-        for (int f = 0; f < NF; ++f) u[f] = (double)U[f * ncell + v];
+        for (int f = 0; f < NF; ++f) u[f] = (double)head[f];
         cell_scales(u, nm.gamma, S);
     }
     for (int f = 0; f < NF; ++f) {
-        double yy = (double)y[f * ncell + v];
+        double yy = (double)yv[f];
         if (nm.clip > 0.0) yy = fmin(fmax(yy, -nm.clip), nm.clip);
         out[f] = S[f] * yy;
     }
+}
+
+// the same, loading cell v of U's head and of y (all loads issued first)
+__device__ __forceinline__ void scaled_output(const float* __restrict__ U, const float* __restrict__ y,
+                                              long long ncell, long long v, const Norm& nm,
+                                              double out[NF])
+{
+    float head[NF] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, yv[NF];
+    for (int f = 0; f < NF; ++f) yv[f] = y[f * ncell + v];
+    if (nm.mode == 1)
+        for (int f = 0; f < NF; ++f) head[f] = U[f * ncell + v];
+    scaled_from(head, yv, nm, out);
 }
 
 __global__ void __launch_bounds__(THREADS)
@@ -966,31 +977,46 @@ mean_final_kernel(const double* __restrict__ partial, int n, long long ncell,
     if (threadIdx.x == 0) cs->bad = 0u;
 }
 
-// Candidate corrected pair (Kahan sum of delta into head/comp), positivity
-// of every candidate cell (FP64 primitive recovery), and per-block sums of
-// the represented change and of its magnitude.
+// The corrected pair of one cell and field: delta = tau (q - mean) rounded
+// to FP32 and Kahan-added into (head, comp).  The check and the commit both
+// call it, so the committed values are the checked ones, bit for bit.
+__device__ __forceinline__ void candidate(float head, float comp, double q, double tau, double mean,
+                                          float& s, float& c2)
+{
+    const float d = (float)(tau * (q - mean));
+    const float yy = d - comp;
+    s = head + yy;
+    c2 = (s - head) - yy;
+}
+
+// Check of the candidate corrected pair, without storing it: positivity of
+// every candidate cell (FP64 primitive recovery) and per-block sums of the
+// represented change and of its magnitude.
 __global__ void __launch_bounds__(THREADS)
-apply_kernel(const float* __restrict__ U, const float* __restrict__ y, long long ncell, Norm nm,
-             gs::Phys k, const CorrState* csr, float* __restrict__ cand,
-             double* __restrict__ partial, CorrState* cs)
+check_kernel(const float* __restrict__ U, const float* __restrict__ y, long long ncell, Norm nm,
+             gs::Phys k, const CorrState* csr, double* __restrict__ partial, CorrState* cs)
 {
     __shared__ double red[2 * NF][THREADS];
-    double moved[NF], mag[NF];
-    for (int f = 0; f < NF; ++f) moved[f] = mag[f] = 0.0;
+    double moved[NF], mag[NF], mean[NF];
+    for (int f = 0; f < NF; ++f) {
+        moved[f] = mag[f] = 0.0;
+        mean[f] = csr->mean[f];
+    }
     bool bad = false;
     for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
          v += (long long)gridDim.x * THREADS) {
         double u[NF], w[NF], q[NF];
-        scaled_output(U, y, ncell, v, nm, q);
+        float head[NF], comp[NF], yv[NF];
         for (int f = 0; f < NF; ++f) {
-            const float head = U[f * ncell + v], comp = U[(NF + f) * ncell + v];
-            const float d = (float)(nm.tau[f] * (q[f] - csr->mean[f]));
-            const float yy = d - comp;
-            const float s = head + yy;
-            const float c2 = (s - head) - yy;
-            cand[f * ncell + v] = s;
-            cand[(NF + f) * ncell + v] = c2;
-            const double change = ((double)s - (double)c2) - ((double)head - (double)comp);
+            head[f] = U[f * ncell + v];
+            comp[f] = U[(NF + f) * ncell + v];
+            yv[f] = y[f * ncell + v];
+        }
+        scaled_from(head, yv, nm, q);
+        for (int f = 0; f < NF; ++f) {
+            float s, c2;
+            candidate(head[f], comp[f], q[f], nm.tau[f], mean[f], s, c2);
+            const double change = ((double)s - (double)c2) - ((double)head[f] - (double)comp[f]);
             moved[f] += change;
             mag[f] += fabs(change);
             u[f] = (double)s - (double)c2;
@@ -1045,13 +1071,33 @@ decide_kernel(const double* __restrict__ partial, int n, CorrState* __restrict__
     }
 }
 
-__global__ void commit_kernel(const float* __restrict__ cand, long long n, const CorrState* __restrict__ cs,
-                              float* __restrict__ U)
+// If the decision accepted the candidate, write it into U in place: each
+// thread recomputes the candidate of its own cells (the same arithmetic as
+// check_kernel) from U and y before overwriting them.
+__global__ void __launch_bounds__(THREADS)
+commit_kernel(float* __restrict__ U, const float* __restrict__ y, long long ncell, Norm nm,
+              const CorrState* __restrict__ cs)
 {
     if (!cs->ok) return;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        U[i] = cand[i];
+    double mean[NF];
+    for (int f = 0; f < NF; ++f) mean[f] = cs->mean[f];
+    for (long long v = (long long)blockIdx.x * THREADS + threadIdx.x; v < ncell;
+         v += (long long)gridDim.x * THREADS) {
+        double q[NF];
+        float head[NF], comp[NF], yv[NF];
+        for (int f = 0; f < NF; ++f) {
+            head[f] = U[f * ncell + v];
+            comp[f] = U[(NF + f) * ncell + v];
+            yv[f] = y[f * ncell + v];
+        }
+        scaled_from(head, yv, nm, q);
+        float s[NF], c2[NF];
+        for (int f = 0; f < NF; ++f) candidate(head[f], comp[f], q[f], nm.tau[f], mean[f], s[f], c2[f]);
+        for (int f = 0; f < NF; ++f) {
+            U[f * ncell + v] = s[f];
+            U[(NF + f) * ncell + v] = c2[f];
+        }
+    }
 }
 
 __global__ void init_corr_kernel(CorrState* cs)
@@ -1106,7 +1152,6 @@ struct gs_cnn {
     float* bpart;   // bias-gradient partials
     double* red;    // reduction partials
     double* host_red;
-    float* cand;    // corrected candidate pair
     CorrState* cs;
     CorrState* host_cs;
 };
@@ -1348,7 +1393,7 @@ int gs_cnn_create(int nx, int ny, int nz, int bc, double gamma, void* stream, gs
         {(void**)&h->h2s, (size_t)n * 3 * 32 * 2},
         {(void**)&h->wpart, (size_t)TAPS * WG_PARTS * 32 * 32 * 4},
         {(void**)&h->bpart, (size_t)32 * BIAS_CHUNKS * 4},
-        {(void**)&h->red, RED_BLOCKS * 2 * NF * 8}, {(void**)&h->cand, (size_t)n * 2 * NF * 4},
+        {(void**)&h->red, RED_BLOCKS * 2 * NF * 8},
         {(void**)&h->cs, sizeof(CorrState)},
     };
     for (auto& a : allocs) *a.p = nullptr;
@@ -1520,11 +1565,11 @@ int gs_cnn_correct(gs_cnn* h, void* U)
                        (const float*)U, h->y, n, h->norm, h->red);
     hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, n,
                        h->cs);
-    hipLaunchKernelGGL(apply_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
-                       h->y, n, h->norm, k, h->cs, h->cand, h->red, h->cs);
+    hipLaunchKernelGGL(check_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
+                       h->y, n, h->norm, k, h->cs, h->red, h->cs);
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, h->cs);
-    hipLaunchKernelGGL(commit_kernel, dim3(grid_for(n * 2 * NF)), dim3(THREADS), 0, h->stream, h->cand,
-                       n * 2 * NF, h->cs, (float*)U);
+    hipLaunchKernelGGL(commit_kernel, dim3(grid_for(n)), dim3(THREADS), 0, h->stream, (float*)U, h->y, n,
+                       h->norm, h->cs);
     e = hipGetLastError();
     return e == hipSuccess ? GS_OK : chip(h, e, "correct");
 }
@@ -1553,7 +1598,7 @@ void gs_cnn_destroy(gs_cnn* h)
     if (!h) return;
     void* ps[] = {h->P, h->G, h->M, h->V, h->wf1, h->wf2, h->wf3, h->wb2, h->wb3, h->x, h->h1,
                   h->h2, h->y, h->dY, h->dYv, h->dA2, h->dA2v, h->dA1, h->dA1v, h->xs, h->h1s,
-                  h->h2s, h->wpart, h->bpart, h->red, h->cand, h->cs};
+                  h->h2s, h->wpart, h->bpart, h->red, h->cs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (h->host_red) (void)hipHostFree(h->host_red);

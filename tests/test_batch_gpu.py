@@ -137,6 +137,27 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
         assert B.autotune(cache) == (ty, kz, True)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_steps_after_autotune_match_problems_alone(dtype):
+    # the autotuner launches every candidate shape (different grids and item
+    # counts) through the same work-item counters; the steps after it, direct
+    # and replayed, must still cover every item of every problem
+    from paper_1812_07977_amd.batch import Batch
+    probs = _problems(DIMS, seed0=650)
+    states = [_state(U0, dtype, "periodic") for U0 in probs]
+    _say(f"case: batch {dtype} periodic, autotune then 4 direct + 3 replayed steps")
+    with Batch(DIMS, states, bc="periodic", dtype=dtype) as B:
+        ty, kz, _ = B.autotune()
+        B.advance(4, graph=False)
+        B.advance(3, graph=True)
+        times = B.times()
+        got = [to_cpu(S) for S in states]
+    for i, U0 in enumerate(probs):
+        ref, t = _alone(U0, dtype, "periodic", 7, (ty, kz))
+        assert np.array_equal(got[i], ref), i
+        assert times[i] == t, i
+
+
 def test_nonphysical_problem_is_reported():
     from paper_1812_07977_amd import NonPhysicalError
     from paper_1812_07977_amd.batch import Batch

@@ -333,6 +333,43 @@ def test_scale_aware_inputs_match_the_oracle():
     assert np.median(err / absum) < 1e-3
 
 
+def test_committed_correction_is_the_kahan_sum_of_the_delta():
+    # the state after an accepted correction, element by element: delta =
+    # tau (y - mean y) rounded to FP32 (mean in FP64), Kahan-added into the
+    # (head, compensation) pair in FP32, from the network output y of the
+    # same state
+    import math
+    import torch
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    from paper_1812_07977_amd.learned import init_params
+    shape = (48, 20, 9)
+    nx, ny, nz = shape
+    U0 = wl.random_plane(nx, ny, nz, seed=17, v=(0.2, -0.1, 0.3))
+    with Fluid(shape, bc="periodic", dtype="f32") as F:
+        S = F.state_from(U0)
+        torch.cuda.synchronize()
+    tau = np.array([2e-3, 3e-3, 3e-3, 3e-3, 5e-3])
+    with _net(shape) as N:
+        N.set_params(init_params(9, out_scale=1.0))
+        N.set_norm(U0.mean(axis=(1, 2, 3)), U0.std(axis=(1, 2, 3)) + 1e-3, tau)
+        y = N.forward(S).cpu().numpy().astype(np.float64)
+        before = S.cpu().numpy()
+        N.correct(S)
+        assert N.counts() == (1, 0)
+        after = S.cpu().numpy()
+    head, comp = before[0], before[1]
+    for f in range(5):
+        mean = math.fsum(y[f].ravel()) / y[f].size
+        d = (tau[f] * (y[f] - mean)).astype(np.float32)
+        yy = d - comp[f]
+        s = head[f] + yy
+        c2 = (s - head[f]) - yy
+        assert np.array_equal(after[0][f], s), f
+        assert np.array_equal(after[1][f], c2), f
+    assert not np.array_equal(after, before)
+
+
 def test_scale_aware_targets_and_clipped_correction():
     import torch
     import workloads as wl
