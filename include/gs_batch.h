@@ -14,11 +14,13 @@
  * caller keeps them alive until gs_batch_destroy.
  *
  * Each step is two launches (substep 1, substep 2 with the fused per-problem
- * max-reduction of the next time step): every workgroup of a persistent grid
- * walks (problem, tile, z-chunk) items; a problem advanced in a batch and
- * alone with the same launch shape gives bit-identical results.  Work runs
- * on a stream of the handle, ordered after and before the caller's stream
- * with events.  Status codes are the GS_* codes of gs_fluid.h.
+ * max-reduction of the next time step): the workgroups of a persistent grid
+ * draw (problem, tile, z-chunk) items from per-XCD device counters that
+ * reset themselves at the end of each launch; a problem advanced in a batch
+ * and alone with the same launch shape gives bit-identical results.  Work
+ * runs on a stream of the handle, ordered after and before the caller's
+ * stream with events; calls on one handle must not overlap.  Status codes are
+ * the GS_* codes of gs_fluid.h.
  */
 #ifndef GS_BATCH_H
 #define GS_BATCH_H
