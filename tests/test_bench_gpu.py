@@ -1,7 +1,8 @@
 """The benchmark's own bookkeeping on a small mesh: one JSON line with the
-fields of its contract, consistent numbers, and an FP32-form error that
+fields of its contract, consistent numbers, an FP32-form error that
 matches what the FP32 tests bound (a reference state advanced past the
-compared step, for instance, shows up as a large error here)."""
+compared step, for instance, shows up as a large error here), and the
+batched form's figures."""
 import json
 import os
 import subprocess
@@ -15,8 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.gpu
 def test_bench_line_on_a_small_mesh():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--size", "64", "--steps", "6",
-           "--warmup", "2", "--forms", "f32", "--no-cpu-baseline"]
-    print("case: bench.py --size 64 --steps 6 --forms f32", flush=True)
+           "--warmup", "2", "--forms", "f32,batch", "--no-cpu-baseline"]
+    print("case: bench.py --size 64 --steps 6 --forms f32,batch", flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
@@ -35,6 +36,16 @@ def test_bench_line_on_a_small_mesh():
     # and time steps: a few FP32 units in the last place
     assert max(f32["linf_rel_err"]) < 1e-5, f32
     assert max(f32["l1_rel_err"]) < 1e-6, f32
+    # the batched form: 64 uneven problems, whole-batch rate against the same
+    # problems one at a time; the batch fills the chip, one small problem
+    # does not
+    for key in ("batch_f64", "batch_f32"):
+        b = line["forms"][key]
+        assert b["value"] > 0 and b["sequential_value"] > 0, b
+        assert b["value"] == pytest.approx(b["speedup_vs_one_at_a_time"] * b["sequential_value"],
+                                           rel=1e-2), b
+        assert b["speedup_vs_one_at_a_time"] > 1.0, b
+        assert b["launch"]["tile_y"] in (8, 16) and b["launch"]["chunk_z"] in (16, 32, 64), b
 
 
 def test_bench_refuses_several_gpus():
