@@ -191,6 +191,12 @@ def test_full_batch_of_64_matches_problems_alone(dtype):
         ref, t = _alone(probs[i], dtype, "periodic", 2, (ty, kz))
         assert np.array_equal(got[i], ref), i
         assert times[i] == t, i
+    if dtype == "f64":
+        # the benchmark's batch in its timed configuration, against the oracle
+        for i in sample:
+            ref, dts = oracle_run(probs[i], "periodic", 2)
+            assert max(rel_linf(got[i], ref)) <= 1e-12, i
+            assert abs(times[i] - float(np.sum(dts))) <= 1e-14 * 2 * float(np.sum(dts)), i
 
 
 @pytest.mark.parametrize("dtype,bc", [("f64", "outflow"), ("f64", "periodic"), ("f32", "outflow")])
