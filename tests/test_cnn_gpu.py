@@ -102,6 +102,31 @@ def test_forward_is_bit_exact_on_exactly_representable_data(shape, bc):
     assert np.array_equal(y, ref)
 
 
+def test_forward_at_128_cubed_sampled_cells_bit_exact():
+    # the mesh size of the learned form's benchmark: the output of a cell
+    # depends only on the input within 3 cells (three 3x3x3 layers), so the
+    # oracle evaluates the network on the 7^3 periodic neighbourhood of each
+    # sampled cell and its centre must equal the GPU's value bit for bit
+    # (dyadic data: every sum exact in FP32)
+    n = 128
+    shape = (n, n, n)
+    rng = np.random.default_rng(21)
+    flat = _dyadic_params(rng)
+    head = (rng.integers(-8, 9, (5, n, n, n)) / 8.0).astype(np.float32)
+    _say("case: cnn forward dyadic 128^3 periodic, sampled cells")
+    with _net(shape) as N:
+        N.set_params(flat)
+        y = N.forward(_pair(head)).cpu().numpy().astype(np.float64)
+    params = _params_from_flat(flat)
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (n - 1, 3, 0), (64, 64, 64)]
+    cells += [tuple(int(c) for c in rng.integers(0, n, 3)) for _ in range(27)]
+    for (k, j, i) in cells:
+        idx = [np.arange(c - 3, c + 4) % n for c in (k, j, i)]
+        patch = head[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]].astype(np.float64)
+        ref, _ = _oracle_forward_bf16(patch, params, ocnn.PERIODIC)
+        assert np.array_equal(y[:, k, j, i], ref[:, 3, 3, 3]), (k, j, i)
+
+
 def test_forward_random_weights_within_fp32_accumulation_bound():
     shape = (32, 16, 12)
     nx, ny, nz = shape
