@@ -126,3 +126,96 @@ def test_product_code_never_reaches_the_oracle():
         if f.endswith((".py", ".c")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1812_07977_amd" not in text and "gs_fluid" not in text, f
+
+
+def _batch_create(count=2, dims=((8, 8, 8), (4, 6, 5)), gamma=1.4, cfl=0.5, bc=0, dtype=0,
+                  states=(256, 512)):
+    """gs_batch_create with host arrays; the state 'pointers' are never
+    dereferenced before the arguments pass validation."""
+    L = _lib()
+    d = (ctypes.c_int * (3 * max(len(dims), 1)))(*[v for t in dims for v in t])
+    s = (ctypes.c_void_p * max(len(states), 1))(*states) if states is not None else None
+    h = ctypes.c_void_p()
+    st = L.gs_batch_create(count, d if dims is not None else None, gamma, cfl, bc, dtype,
+                           s, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("over", [
+    dict(count=0), dict(count=-3), dict(count=1 << 17),
+    dict(dims=((0, 8, 8), (4, 6, 5))), dict(dims=((8, 8, 8), (4, -1, 5))),
+    dict(states=(256, 0)), dict(states=(256, 520)),
+    dict(gamma=1.0), dict(gamma=math.nan), dict(cfl=0.0), dict(cfl=1.01),
+    dict(bc=3), dict(dtype=5),
+])
+def test_batch_create_rejects_bad_arguments(over):
+    st, h = _batch_create(**over)
+    assert st == lib_mod.GS_ERR_ARG
+    assert not h.value
+    assert _lib().gs_batch_last_error(None).decode()
+
+
+def test_batch_create_rejects_null_arrays():
+    L = _lib()
+    h = ctypes.c_void_p()
+    s = (ctypes.c_void_p * 1)(256)
+    d = (ctypes.c_int * 3)(8, 8, 8)
+    assert L.gs_batch_create(1, None, 1.4, 0.5, 0, 0, s, None, ctypes.byref(h)) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_create(1, d, 1.4, 0.5, 0, 0, None, None, ctypes.byref(h)) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_create(1, d, 1.4, 0.5, 0, 0, s, None, None) == lib_mod.GS_ERR_ARG
+
+
+def test_batch_null_handle_calls_are_argument_errors():
+    L = _lib()
+    i = ctypes.c_int()
+    t = (ctypes.c_double * 4)()
+    assert L.gs_batch_set_launch(None, 0, 0) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_autotune(None, None, ctypes.byref(i), ctypes.byref(i),
+                               ctypes.byref(i)) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_advance(None, 1, 0.0, 1) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_times(None, t) == lib_mod.GS_ERR_ARG
+    assert L.gs_batch_sync(None) == lib_mod.GS_ERR_ARG
+    L.gs_batch_destroy(None)
+    assert L.gs_batch_last_error(None) is not None
+
+
+def test_cnn_parameter_count():
+    # W1 32x5x27 + b1 32, W2 32x32x27 + b2 32, W3 5x32x27 + b3 5
+    assert _lib().gs_cnn_param_count() == 32 * 5 * 27 + 32 + 32 * 32 * 27 + 32 + 5 * 32 * 27 + 5
+
+
+@pytest.mark.parametrize("args", [
+    (0, 8, 8, 1, 1.4), (8, -1, 8, 1, 1.4), (8, 8, 0, 1, 1.4),
+    (1 << 10, 1 << 10, 1 << 9, 1, 1.4),
+    (8, 8, 8, 2, 1.4), (8, 8, 8, -1, 1.4),
+    (8, 8, 8, 1, 1.0), (8, 8, 8, 1, math.inf),
+])
+def test_cnn_create_rejects_bad_arguments(args):
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.gs_cnn_create(*args, None, ctypes.byref(h)) == lib_mod.GS_ERR_ARG
+    assert not h.value
+    assert L.gs_cnn_last_error(None).decode()
+    assert L.gs_cnn_create(8, 8, 8, 1, 1.4, None, None) == lib_mod.GS_ERR_ARG
+
+
+def test_cnn_null_handle_calls_are_argument_errors():
+    L = _lib()
+    d = ctypes.c_double()
+    i = ctypes.c_int()
+    v = (ctypes.c_double * 5)()
+    E = lib_mod.GS_ERR_ARG
+    assert L.gs_cnn_set_params(None, None) == E
+    assert L.gs_cnn_get_params(None, None) == E
+    assert L.gs_cnn_set_norm(None, v, v, v) == E
+    assert L.gs_cnn_set_features(None, 0, 0.0) == E
+    assert L.gs_cnn_forward(None, None, None) == E
+    assert L.gs_cnn_restrict(None, None, None) == E
+    assert L.gs_cnn_make_target(None, None, None, None) == E
+    assert L.gs_cnn_gradients(None, None, None, None, ctypes.byref(d)) == E
+    assert L.gs_cnn_train_step(None, None, None, 1e-3, ctypes.byref(d)) == E
+    assert L.gs_cnn_correct(None, None) == E
+    assert L.gs_cnn_counts(None, ctypes.byref(i), ctypes.byref(i)) == E
+    assert L.gs_cnn_set_stream(None, None) == E
+    L.gs_cnn_destroy(None)
+    assert L.gs_cnn_last_error(None) is not None
