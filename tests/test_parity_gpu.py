@@ -342,3 +342,37 @@ def test_host_dt_and_device_dt_interleave():
             F.step(U, F.dt(U))
         F.sync()
     assert np.array_equal(to_cpu(U), ref)
+
+
+def test_two_handles_on_two_streams_match_each_alone():
+    # two solvers with their own streams, device words and workspaces, their
+    # advances queued concurrently (FP64 and FP32, different meshes), give
+    # the states each gives alone
+    import torch
+    from paper_1812_07977_amd import Fluid
+    cases = [((48, 40, 36), "f64", wl.random_plane(48, 40, 36, seed=5, v=(0.2, 0.1, -0.3))),
+             ((40, 32, 24), "f32", wl.random_plane(40, 32, 24, seed=6))]
+    _say("case: two handles on two streams, 12 steps each, f64 48x40x36 and f32 40x32x24")
+    alone = []
+    for shape, dtype, U0 in cases:
+        with Fluid(shape, bc="periodic", dtype=dtype) as F:
+            S = F.state_from(U0)
+            F.advance(S, 12)
+            alone.append((to_cpu(S), F.time))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    solvers = [Fluid(shape, bc="periodic", dtype=dtype, stream=s)
+               for (shape, dtype, _), s in zip(cases, streams)]
+    try:
+        states = [F.state_from(U0) for F, (_, _, U0) in zip(solvers, cases)]
+        torch.cuda.synchronize()
+        for _ in range(3):
+            for F, S in zip(solvers, states):
+                F.advance(S, 4)
+        for F in solvers:
+            F.sync()
+        for (ref, t), F, S in zip(alone, solvers, states):
+            assert np.array_equal(to_cpu(S), ref)
+            assert F.time == t
+    finally:
+        for F in solvers:
+            F.close()
