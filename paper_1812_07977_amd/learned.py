@@ -219,6 +219,18 @@ def _solvers(n, gamma, cfl):
     return fine, coarse
 
 
+def _advance_to(F, U, t_end, chunk=2, limit=64):
+    """Advance the fine solve F (device dt) to t_end in chunks of `chunk`
+    steps until its device time reaches t_end.  Steps past t_end take dt = 0
+    and leave the state unchanged, but each still costs a full step, so a
+    fixed generous step count would mostly compute nothing."""
+    for _ in range(limit):
+        F.advance(U, chunk, t_end)
+        if not F.time < t_end:
+            return
+    raise RuntimeError(f"fine solve did not reach t = {t_end} in {chunk * limit} steps")
+
+
 def generate_samples(net, fine_states, steps, gamma=1.4, cfl=0.5, stride=1):
     """Training pairs from fine FP64 runs.  For each initial fine state (a
     float64 GPU tensor (5, 2n, 2n, 2n)) and each of `steps` coarse steps: the
@@ -239,7 +251,7 @@ def generate_samples(net, fine_states, steps, gamma=1.4, cfl=0.5, stride=1):
             dt = C.dt(Uc)
             C.step(Uc, dt)
             F.time = t
-            F.advance(Uf, 8, t + dt)
+            _advance_to(F, Uf, t + dt)
             t += dt
             if k % stride == stride - 1:
                 inputs.append(Uc)
@@ -383,7 +395,7 @@ def evaluate(net, fine_state, steps, gamma=1.4, cfl=0.5, with_net=True, every=0)
             C.step(corr, dt)
             net.correct(corr)
         F.time = t
-        F.advance(Uf, 8, t + dt)
+        _advance_to(F, Uf, t + dt)
         t += dt
         if every and (k + 1) % every == 0:
             e = _errors(net, Uf, plain, corr if with_net else None)
