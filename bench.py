@@ -1,8 +1,9 @@
 """Benchmark: FP64 RK2 finite-volume Euler steps per second on one MI355X,
-and the compensated FP32 form beside it.
+with the other per-GPU cases and the forms built on the step beside it.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--size 512]
                     [--case sine|plane] [--no-cpu-baseline] [--no-forms]
+                    [--no-cases] [--case-sizes 512,256]
                     [--forms f32,batch,learned] [--learned-iters N] [--copy-probe MIB]
 
 A step is one RK2 step of the whole hot path on the periodic cube: the two
@@ -12,19 +13,25 @@ sequence).  Inputs are synthetic and already resident in HBM when timing
 starts: the smooth case rho = 1 + 0.2 sin(2 pi (x+y+z)), v = (1,1,1), p = 1
 (exact cell averages), or the seeded random-plane Riemann case (seed 0).
 
-Prints one JSON line with the cell-update rate, the roofline of the dominant
-kernel (per-launch algorithmic HBM bytes over its average event-timed
-duration, against the 8 TB/s HBM3E peak and against a measured
-device-to-device copy) and the CPU oracle timed on a bounded sample on the
-host cores (all threads; then one eighth of them and one, on a smaller
+Prints one JSON line with the cell-update rate of the timed block (no
+per-kernel events inside it), the roofline of the dominant kernel
+(per-launch algorithmic HBM bytes over its average event-timed duration,
+from a second block of the same length with HIP events around every launch,
+against the 8 TB/s HBM3E peak and against the ceiling the library's
+streaming probe measures for the kernel's read:write mix), the step-level
+fraction of the HBM peak, and the CPU oracle timed on a bounded sample on
+the host cores (all threads; then one eighth of them and one, on a smaller
 sample).  After the reported block of steps, four more blocks of the same
 length give the spread of the rate (reported with their median), and 20
 steps of the host-synchronised path (gs_fluid_dt, then gs_fluid_step) give
-its rate.  Under "forms" the FP32 form is timed the
-same way on the same input, with its speedup over FP64 and its L1 and
-L-infinity error per field against the FP64 solution of the same input after
-the same steps (the FP32 run is driven with the FP64 run's time steps; the
-FP64 path itself matches the CPU oracle to 1e-12).
+its rate.  Under "cases" the random-plane Riemann case and the smooth case
+at 512^3 and 256^3 are timed the same way, FP64 and FP32 (with the FP32
+error per field on the 512^3 Riemann case).  Under "forms" the FP32 form is
+timed the same way on the headline input, with its speedup over FP64 and
+its L1 and L-infinity error per field against the FP64 solution of the same
+input after the same steps (the FP32 run is driven with the FP64 run's time
+steps; the FP64 path itself matches the CPU oracle to 1e-12); then the
+batched and learned-correction forms.
 """
 import argparse
 import hashlib
@@ -121,11 +128,14 @@ def cpu_baseline(case, size=256, steps=10):
             "by_threads_sample": f"{case} case on a 128^3 periodic mesh, 2 RK2 steps"}
 
 
-def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_steps=0):
+def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_steps=0,
+              case="sine"):
     """Warm-up and timed gs_fluid_advance runs of one form from U0; returns
-    the figures and the dt of every step (warm-up first).  repeats > 1 times
-    that many blocks of `steps` steps in all (the first is the reported
-    one); host_steps > 0 then also times that many host-dt steps."""
+    the figures and the dt of every step (warm-up first).  The reported
+    block of `steps` steps runs without per-kernel events; repeats > 1 times
+    that many blocks in all (the first is the reported one).  Then one more
+    block of `steps` steps with HIP events around every launch gives the
+    per-kernel durations, and host_steps > 0 times that many host-dt steps."""
     import torch
     from paper_1812_07977_amd import Fluid
     F = Fluid((n, n, n), gamma=1.4, cfl=0.5, bc="periodic", dtype=dtype)
@@ -136,9 +146,6 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
     if warmup:
         F.advance(S, warmup, 0.0, log_w)
     F.sync()
-    F.profile(True)
-    for k in range(3):
-        F.kernel_ms(k)          # discard warm-up events
 
     stream = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -150,7 +157,6 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
     F.sync()
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
-    per_kernel = {k: F.kernel_ms(k) for k in range(3)}
     t_sim = F.time
     # a copy: for FP64 the state itself is returned, and the blocks below
     # advance it further
@@ -168,6 +174,19 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
             F.sync()
             reps.append(t0.elapsed_time(t1))
         extra["repeat_ms"] = reps
+    # per-kernel durations: HIP events the library records on its stream
+    # around every launch, in a block of its own
+    F.profile(True)
+    for k in range(3):
+        F.kernel_ms(k)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    F.advance(S, steps)
+    t1.record(stream)
+    F.sync()
+    per_kernel = {k: F.kernel_ms(k) for k in range(3)}
+    extra["profiled_block_ms"] = t0.elapsed_time(t1)
+    F.profile(False)
     if host_steps:
         # the host-synchronised path: a reduction and a read-back of dt
         # before every step
@@ -179,28 +198,44 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
         F.sync()
         extra["host_dt_ms"] = t0.elapsed_time(t1)
         extra["host_steps"] = host_steps
-    F.profile(False)
     F.close()
     return {"total_ms": total_ms, "per_kernel": per_kernel, "t_sim": t_sim, **extra}, dts, result
 
 
-def copy_ceiling_gbs(mib=2048, reps=3):
-    """Measured HBM ceiling: the best of `reps` device-to-device copies of
-    mib MiB (read and write bytes over the event-timed duration)."""
+def hbm_ceilings(mib=2048, reps=3):
+    """Measured HBM ceilings from the library's streaming probe
+    (gs_fluid_stream_probe): the best of `reps` event-timed runs over arrays
+    of mib MiB for each read:write mix (copy 1:1 and add 2:1, the mixes of
+    the two substeps) with and without non-temporal stores, in GB/s of bytes
+    read plus written; and torch's device-to-device copy for comparison."""
     import torch
-    a = torch.ones(mib * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
+    from paper_1812_07977_amd import stream_probe
+    nel = mib * 1024 * 1024 // 8
+    a = torch.rand(nel, dtype=torch.float64, device="cuda")
+    b = torch.rand(nel, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    best = 0.0
-    for _ in range(reps + 1):      # the first copy is a warm-up
-        torch.cuda.synchronize()
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        best = max(best, 2.0 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
-    del a, b
-    return best
+    out = {}
+
+    def best(fn, nbytes):
+        top = 0.0
+        for _ in range(reps + 1):      # the first run is a warm-up
+            torch.cuda.synchronize()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            top = max(top, nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+        return round(top, 1)
+
+    for nt in (False, True):
+        tag = "_nt" if nt else ""
+        out["copy_1to1" + tag] = best(lambda: stream_probe(a, c, nontemporal=nt), 2 * nel * 8)
+        out["add_2to1" + tag] = best(lambda: stream_probe(a, c, b=b, nontemporal=nt), 3 * nel * 8)
+    out["torch_copy"] = best(lambda: c.copy_(a), 2 * nel * 8)
+    del a, b, c
+    return out
 
 
 def roofline(dtype, n, case, per_kernel):
@@ -452,6 +487,71 @@ def batched_form(dtype, steps=20, count=64, seed=1):
     }
 
 
+def add_ceiling(roof, ceil):
+    """The dominant kernel's rate against the probe's ceiling for its
+    read:write mix (the second substep reads two arrays per array written:
+    the add mix; the first reads one: the copy mix), the better of the
+    plain and non-temporal stores."""
+    mix = "add_2to1" if "substep 2" in roof["kernel"] else "copy_1to1"
+    c = max(ceil[mix], ceil[mix + "_nt"])
+    roof["ceiling_gbs"] = c
+    roof["ceiling_mix"] = mix
+    roof["frac_of_ceiling"] = round(roof["achieved"] / c, 4)
+
+
+def case_entry(case, n, dtype, steps, warmup, ceil, U0=None):
+    """One more timed configuration: the same measurement as the headline
+    (device dt, `steps` steps after `warmup`) for another case, size or
+    form; returns (entry, dts, FP64 result or None, U0)."""
+    if U0 is None:
+        U0 = make_input(n, case)
+    r, dts, res = timed_run(U0, n, dtype, steps, warmup, 0, 0, case=case)
+    cells = n ** 3
+    ms = r["total_ms"] / steps
+    roof, _ = roofline(dtype, n, case, r["per_kernel"])
+    add_ceiling(roof, ceil)
+    bpc = 200.0 if dtype == "f64" else 180.0
+    entry = {
+        "workload": f"{'sine' if case == 'sine' else 'random-plane Riemann (seed 0)'} {n}^3 "
+                    f"periodic, {dtype.upper()}, device dt",
+        "value": cells * steps / (r["total_ms"] / 1e3), "unit": "cell-updates/s",
+        "ms_per_step": round(ms, 4),
+        "hbm_gbs_algorithmic": round(bpc * cells / (ms / 1e3) / 1e9, 1),
+        "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
+                              for k, v in r["per_kernel"].items()},
+        "roofline": {k: roof[k] for k in ("kernel", "achieved", "frac", "frac_of_ceiling",
+                                          "avg_launch_ms")},
+    }
+    return entry, dts, res, U0
+
+
+def other_cases(args, ceil, headline):
+    """The rest of the per-GPU configurations beside the headline: the
+    random-plane Riemann case (seed 0) and the smooth case at each of the
+    sizes in --case-sizes (default 512^3 and 256^3), FP64 and the FP32 form;
+    for the FP32 form of the Riemann case at the largest size also its L1 /
+    L-infinity error per field against FP64."""
+    out = {}
+    sizes = [int(v) for v in args.case_sizes.split(",") if v]
+    for n, case in [(m, c) for m in sizes for c in ("plane", "sine")]:
+        if (case, n) == headline:
+            continue
+        print(f"bench: case {case} {n}^3", file=sys.stderr, flush=True)
+        e64, dts, U64, U0 = case_entry(case, n, "f64", args.steps, args.warmup, ceil)
+        e32, _, _, _ = case_entry(case, n, "f32", args.steps, args.warmup, ceil, U0=U0)
+        e32["speedup_vs_f64"] = round(e64["ms_per_step"] / e32["ms_per_step"], 3)
+        if n == max(sizes) and case == "plane":
+            l1, linf = f32_error(U0, n, dts, U64)
+            e32["l1_rel_err"], e32["linf_rel_err"] = l1, linf
+            e32["error_vs"] = (f"FP64 solution of the same input after the same "
+                               f"{args.warmup + args.steps} steps (same dt sequence)")
+        del U64, U0
+        key = f"{case}_{n}"
+        out[key + "_f64"] = e64
+        out[key + "_f32"] = e32
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +563,10 @@ def main():
     ap.add_argument("--chunk-z", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the FP64 form only")
+    ap.add_argument("--no-cases", action="store_true",
+                    help="skip the other per-GPU cases (512^3 Riemann, 256^3 sine and Riemann)")
+    ap.add_argument("--case-sizes", default="512,256",
+                    help="mesh sizes of the other per-GPU cases (comma list)")
     ap.add_argument("--forms", default="f32,batch,learned",
                     help="comma list of the forms to run beside FP64: f32, batch, learned")
     ap.add_argument("--learned-iters", type=int, default=8000,
@@ -494,15 +598,17 @@ def main():
         del a, b
 
     r64, dts64, U64 = timed_run(U0, n, "f64", args.steps, args.warmup, args.tile_y, args.chunk_z,
-                                repeats=5, host_steps=20)
-    copy_gbs = copy_ceiling_gbs()
+                                repeats=5, host_steps=20, case=args.case)
+    print("bench: HBM ceilings (streaming probe)", file=sys.stderr, flush=True)
+    ceil = hbm_ceilings()
 
     cells = n ** 3
     ms_per_step = r64["total_ms"] / args.steps
     rate = cells * args.steps / (r64["total_ms"] / 1e3)
     alg_bytes_step = 200.0 * cells + 40.0 * cells / args.steps
     roof, alu = roofline("f64", n, args.case, r64["per_kernel"])
-    roof["frac_of_copy_ceiling"] = round(roof["achieved"] / copy_gbs, 4)
+    add_ceiling(roof, ceil)
+    step_gbs = alg_bytes_step / (ms_per_step / 1e3) / 1e9
 
     line = {
         "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1,
@@ -512,9 +618,13 @@ def main():
         "config": {"workload": f"{args.case} {n}^3 periodic cube, FP64, minmod PLM + HLL + RK2, "
                                f"CFL 0.5, device dt", "grid": [n, n, n], "case": args.case,
                    "gamma": 1.4, "cfl": 0.5, "bc": "periodic"},
-        "hbm_gbs_algorithmic": round(alg_bytes_step / (ms_per_step / 1e3) / 1e9, 1),
+        "hbm_gbs_algorithmic": round(step_gbs, 1),
+        "step_frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
         "per_kernel_avg_ms": {KERNEL_NAMES[k]: round(v[0] / max(v[1], 1), 4)
                               for k, v in r64["per_kernel"].items()},
+        "per_kernel_note": "HIP events around every launch, in a separate block of the same "
+                           f"{args.steps} steps right after the timed one (the timed block "
+                           "records no per-kernel events)",
         "sim_time": r64["t_sim"],
         "repeats": {"blocks": len(r64["repeat_ms"]), "steps_each": args.steps,
                     "cell_updates_per_s": [round(cells * args.steps / (t / 1e3)) for t in r64["repeat_ms"]],
@@ -524,12 +634,15 @@ def main():
                     "ms_per_step": r64["host_dt_ms"] / r64["host_steps"],
                     "note": "gs_fluid_dt (reduction + 8-byte read-back + sync) then gs_fluid_step, "
                             "240 B/cell-update"},
-        "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
+        "hbm_ceiling_gbs": ceil,
         "roofline": roof,
         "alu": alu,
         "context": "paper: ~12X wall-time speedup of one V100 over 7 Power9 cores "
                    "(Summit, 256^3 per rank, incl. host transfers)",
     }
+
+    if not args.no_cases:
+        line["cases"] = other_cases(args, ceil, (args.case, n))
 
     forms = set() if args.no_forms else {f for f in args.forms.split(",") if f}
     line["forms"] = {}
@@ -538,6 +651,7 @@ def main():
         r32, _, _ = timed_run(U0, n, "f32", args.steps, args.warmup, args.tile_y, args.chunk_z)
         ms32 = r32["total_ms"] / args.steps
         roof32, alu32 = roofline("f32", n, args.case, r32["per_kernel"])
+        add_ceiling(roof32, ceil)
         print("bench: FP32 form error against FP64", file=sys.stderr, flush=True)
         l1, linf = f32_error(U0, n, dts64, U64)
         line["forms"]["f32"] = {

@@ -115,9 +115,14 @@ int gs_cnn_train_step(gs_cnn* h, const void* U, const float* target, float lr, d
 /*
  * Apply the correction to the state U in place (head and compensation,
  * Kahan-summed).  Falls back to leaving U unchanged when the corrected state
- * would hold a cell with density or pressure <= 0 or not finite, or when
- * the correction would move a conserved total by more than 1e-5 of its
- * magnitude; the decision is taken on the device, no host wait.
+ * would hold a cell with density or pressure <= 0 or not finite, or when,
+ * for some conserved field, the summed change of the represented state
+ * (head - compensation) exceeds 1e-5 of the summed magnitudes of the
+ * per-cell changes (or either sum is not finite).  Since the mean is removed
+ * in FP64 before the per-cell deltas are rounded to FP32, a finite
+ * correction moves each total by rounding only and passes this second
+ * check; it guards against rounding blow-up and non-finite sums.  The
+ * decision is taken on the device, no host wait.
  */
 int gs_cnn_correct(gs_cnn* h, void* U);
 

@@ -151,7 +151,9 @@ int gs_fluid_sync(gs_fluid* h);
 int gs_fluid_get_time(gs_fluid* h, double* t_out);
 int gs_fluid_set_time(gs_fluid* h, double t);
 
-/* Change the stream used by later calls. */
+/* Change the stream used by later calls.  The new stream first waits for
+ * the work already queued on the old one (an event recorded there), since
+ * that work still uses the handle's workspace and device words. */
 int gs_fluid_set_stream(gs_fluid* h, void* stream);
 
 /*
@@ -175,6 +177,21 @@ int gs_fluid_kernel_ms(gs_fluid* h, int kernel, double* total_ms, int* launches)
 
 /* Bytes of device memory the handle allocates for a mesh (workspace). */
 long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype);
+
+/*
+ * HBM streaming probe, the ceiling the stage kernels' bandwidth is compared
+ * with (not a step of the paper's algorithm; the paper argues its kernels
+ * are bound by memory bandwidth, Section 4).  Queues one kernel on stream
+ * (hipStream_t or NULL) computing c[i] = a[i] (b NULL: one read per write,
+ * the first substep's mix) or c[i] = a[i] + b[i] (two reads per write, the
+ * second substep's mix) for i < n, FP64, in 16-byte vectors.  flags bit 0:
+ * non-temporal stores.  a, b, c: device arrays of n doubles, 16-byte
+ * aligned, c not overlapping a or b; n even and > 0.  Does not wait; time
+ * it with events on the same stream.  Errors: GS_ERR_ARG (message from
+ * gs_fluid_last_error(NULL)), GS_ERR_HIP on a failed launch.
+ */
+int gs_fluid_stream_probe(const double* a, const double* b, double* c, long long n,
+                          int flags, void* stream);
 
 /* Release the handle and its workspace (does not wait for the stream; the
  * caller must not destroy a handle with work in flight).  NULL: no-op. */

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgs_oracle.so")
+# GS_ORACLE_LIB selects another build of the same source (the sanitizer
+# build of build.py --sanitize)
+LIB_PATH = os.environ.get("GS_ORACLE_LIB") or os.path.join(HERE, "libgs_oracle.so")
 
 _lib = None
 

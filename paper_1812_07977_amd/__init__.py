@@ -15,7 +15,8 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC", "F64", "F32"]
+__all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC", "F64", "F32",
+           "stream_probe"]
 
 OUTFLOW = _lib.GS_BC_OUTFLOW
 PERIODIC = _lib.GS_BC_PERIODIC
@@ -232,3 +233,19 @@ class Fluid:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def stream_probe(a, c, b=None, nontemporal=False, stream=None):
+    """Queue the HBM streaming probe on `stream` (default: the current
+    stream): c = a, or c = a + b when b is given.  a, b, c: contiguous
+    float64 GPU tensors of the same even number of elements."""
+    import torch
+    ts = [a, c] + ([b] if b is not None else [])
+    for t in ts:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda \
+                or not t.is_contiguous() or t.numel() != a.numel():
+            raise ValueError("a, b, c must be contiguous float64 GPU tensors of one size")
+    bp = ctypes.c_void_p(b.data_ptr()) if b is not None else None
+    _check(_lib.lib().gs_fluid_stream_probe(ctypes.c_void_p(a.data_ptr()), bp,
+                                            ctypes.c_void_p(c.data_ptr()), int(a.numel()),
+                                            1 if nontemporal else 0, _stream_ptr(stream)))

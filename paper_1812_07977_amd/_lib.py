@@ -8,7 +8,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgs_fluid.so")
+# GS_FLUID_LIB selects another build of the same sources (the host-sanitized
+# build used by the CPU sanitizer check)
+LIB_PATH = os.environ.get("GS_FLUID_LIB") or os.path.join(HERE, "libgs_fluid.so")
 
 GS_OK = 0
 GS_ERR_ARG = -1
@@ -45,6 +47,7 @@ SIGNATURES = [
     ("gs_fluid_workspace_bytes", _LL, [_I, _I, _I, _I]),
     ("gs_fluid_destroy", None, [_VP]),
     ("gs_fluid_last_error", ctypes.c_char_p, [_VP]),
+    ("gs_fluid_stream_probe", _I, [_VP, _VP, _VP, _LL, _I, _VP]),
     # batched form (include/gs_batch.h)
     ("gs_batch_create", _I, [_I, _VP, _D, _D, _I, _I, _VP, _VP, ctypes.POINTER(_VP)]),
     ("gs_batch_set_launch", _I, [_VP, _I, _I]),

@@ -1589,7 +1589,19 @@ int gs_cnn_counts(gs_cnn* h, int* applied, int* fallbacks)
 int gs_cnn_set_stream(gs_cnn* h, void* stream)
 {
     if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
-    h->stream = (hipStream_t)stream;
+    hipStream_t ns = (hipStream_t)stream;
+    if (ns != h->stream) {
+        // kernels queued on the old stream still use the handle's buffers:
+        // the new stream waits for them before any later call
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+        if (ev) (void)hipEventDestroy(ev);
+        if (e != hipSuccess)
+            return cfail(h, GS_ERR_HIP, std::string("set_stream ordering: ") + hipGetErrorString(e));
+    }
+    h->stream = ns;
     return GS_OK;
 }
 

@@ -159,6 +159,41 @@ totals_final_kernel(const double* __restrict__ partial, int n, DevState* __restr
 
 __global__ void set_time_kernel(DevState* st, int parity, double t) { st->t[parity] = t; }
 
+// HBM streaming probe: c = a (one read per write) or c = a + b (two reads
+// per write), the read:write mixes of the two substeps, over n doubles as
+// 16-byte vectors.  Each thread moves PROBE_UNROLL vectors, 256 apart, all
+// loads issued before the first store.  NTS: non-temporal stores.
+constexpr int PROBE_THREADS = 256;
+constexpr int PROBE_UNROLL = 4;
+typedef double probe_d2 __attribute__((ext_vector_type(2)));
+
+template <bool TWO, bool NTS>
+__global__ void __launch_bounds__(PROBE_THREADS)
+stream_probe_kernel(const probe_d2* __restrict__ a, const probe_d2* __restrict__ b,
+                    probe_d2* __restrict__ c, long long n2)
+{
+    const long long base = (long long)blockIdx.x * PROBE_THREADS * PROBE_UNROLL + threadIdx.x;
+    probe_d2 va[PROBE_UNROLL], vb[PROBE_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; ++u) {
+        const long long i = base + (long long)u * PROBE_THREADS;
+        if (i < n2) {
+            va[u] = a[i];
+            if (TWO) vb[u] = b[i];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; ++u) {
+        const long long i = base + (long long)u * PROBE_THREADS;
+        if (i < n2) {
+            probe_d2 r = va[u];
+            if (TWO) r = r + vb[u];
+            if (NTS) __builtin_nontemporal_store(r, c + i);
+            else c[i] = r;
+        }
+    }
+}
+
 }  // namespace gs
 
 // ===========================================================================
@@ -670,7 +705,18 @@ int gs_fluid_set_time(gs_fluid* h, double t)
 int gs_fluid_set_stream(gs_fluid* h, void* stream)
 {
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
-    h->stream = (hipStream_t)stream;
+    hipStream_t ns = (hipStream_t)stream;
+    if (ns != h->stream) {
+        // work queued on the old stream still uses the handle's workspace and
+        // device words: the new stream waits for it before any later call
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+        if (ev) (void)hipEventDestroy(ev);
+        if (e != hipSuccess) return hip_fail(h, e, "set_stream ordering");
+    }
+    h->stream = ns;
     return GS_OK;
 }
 
@@ -730,6 +776,36 @@ void gs_fluid_destroy(gs_fluid* h)
     if (h->st) (void)hipFree(h->st);
     if (h->host_st) (void)hipHostFree(h->host_st);
     delete h;
+}
+
+int gs_fluid_stream_probe(const double* a, const double* b, double* c, long long n, int flags,
+                          void* stream)
+{
+    g_create_error.clear();
+    if (!a || !c) return fail(nullptr, GS_ERR_ARG, "a or c is NULL");
+    if (!aligned_to(a, 16) || !aligned_to(c, 16) || (b && !aligned_to(b, 16)))
+        return fail(nullptr, GS_ERR_ARG, "a, b and c must be 16-byte aligned");
+    if (n <= 0 || (n & 1)) return fail(nullptr, GS_ERR_ARG, "n must be even and > 0");
+    if (flags & ~1) return fail(nullptr, GS_ERR_ARG, "unknown flags");
+    const long long n2 = n / 2;
+    const long long per = (long long)PROBE_THREADS * PROBE_UNROLL;
+    const long long blocks = (n2 + per - 1) / per;
+    if (blocks > 0x7fffffffLL) return fail(nullptr, GS_ERR_ARG, "n too large");
+    hipStream_t st = (hipStream_t)stream;
+    const probe_d2* A = (const probe_d2*)a;
+    const probe_d2* B = (const probe_d2*)b;
+    probe_d2* C = (probe_d2*)c;
+    const bool nts = flags & 1;
+    dim3 grid((unsigned)blocks), block(PROBE_THREADS);
+    if (b) {
+        if (nts) hipLaunchKernelGGL((stream_probe_kernel<true, true>), grid, block, 0, st, A, B, C, n2);
+        else hipLaunchKernelGGL((stream_probe_kernel<true, false>), grid, block, 0, st, A, B, C, n2);
+    } else {
+        if (nts) hipLaunchKernelGGL((stream_probe_kernel<false, true>), grid, block, 0, st, A, B, C, n2);
+        else hipLaunchKernelGGL((stream_probe_kernel<false, false>), grid, block, 0, st, A, B, C, n2);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GS_OK : hip_fail(nullptr, e, "stream probe launch");
 }
 
 const char* gs_fluid_last_error(const gs_fluid* h)

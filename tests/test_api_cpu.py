@@ -219,3 +219,29 @@ def test_cnn_null_handle_calls_are_argument_errors():
     assert L.gs_cnn_set_stream(None, None) == E
     L.gs_cnn_destroy(None)
     assert L.gs_cnn_last_error(None) is not None
+
+
+@pytest.mark.parametrize("case", ["a_null", "c_null", "a_misaligned", "b_misaligned", "n_odd",
+                                  "n_zero", "flags"])
+def test_stream_probe_rejects_bad_arguments(case):
+    # every case fails validation before a launch, so the fake (aligned,
+    # never dereferenced) pointers are safe on any machine
+    L = _lib()
+    a, b, c = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    n, flags = 1024, 0
+    if case == "a_null":
+        a = None
+    elif case == "c_null":
+        c = None
+    elif case == "a_misaligned":
+        a = ctypes.c_void_p((1 << 20) + 8)
+    elif case == "b_misaligned":
+        b = ctypes.c_void_p((2 << 20) + 8)
+    elif case == "n_odd":
+        n = 1023
+    elif case == "n_zero":
+        n = 0
+    else:
+        flags = 2
+    assert L.gs_fluid_stream_probe(a, b, c, n, flags, None) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_last_error(None).decode()

@@ -16,8 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.gpu
 def test_bench_line_on_a_small_mesh():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--size", "64", "--steps", "6",
-           "--warmup", "2", "--forms", "f32,batch", "--no-cpu-baseline"]
-    print("case: bench.py --size 64 --steps 6 --forms f32,batch", flush=True)
+           "--warmup", "2", "--forms", "f32,batch", "--no-cpu-baseline", "--case-sizes", "48,64"]
+    print("case: bench.py --size 64 --steps 6 --forms f32,batch --case-sizes 48,64", flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
@@ -30,7 +30,23 @@ def test_bench_line_on_a_small_mesh():
     roof = line["roofline"]
     assert 0 < roof["frac"] < 1 and roof["achieved"] == pytest.approx(roof["frac"] * roof["peak"], rel=1e-3)
     assert line["repeats"]["blocks"] == 5 and line["host_dt"]["steps"] == 20
-    assert line["hbm_copy_ceiling_gbs"] > 0
+    ceil = line["hbm_ceiling_gbs"]
+    for key in ("copy_1to1", "copy_1to1_nt", "add_2to1", "add_2to1_nt", "torch_copy"):
+        assert ceil[key] > 0, key
+    assert roof["frac_of_ceiling"] == pytest.approx(roof["achieved"] / roof["ceiling_gbs"], rel=1e-3)
+    assert line["step_frac_of_hbm_peak"] == pytest.approx(line["hbm_gbs_algorithmic"] / 8000.0,
+                                                          rel=1e-3)
+    # the other cases: the Riemann case at both sizes, the smooth case at the
+    # size that is not the headline's; FP64 and FP32 each
+    cases = line["cases"]
+    assert sorted(cases) == sorted(["plane_48_f64", "plane_48_f32", "sine_48_f64", "sine_48_f32",
+                                    "plane_64_f64", "plane_64_f32"]), sorted(cases)
+    for key, c in cases.items():
+        n = int(key.split("_")[1])
+        assert c["value"] == pytest.approx(n ** 3 / (c["ms_per_step"] / 1e3), rel=1e-3), key
+        assert 0 < c["roofline"]["frac"] < 1, key
+    assert max(cases["plane_64_f32"]["linf_rel_err"]) < 1e-5
+    assert max(cases["plane_64_f32"]["l1_rel_err"]) < 1e-6
     f32 = line["forms"]["f32"]
     # 8 steps of the FP32 form against the FP64 solution of the same input
     # and time steps: a few FP32 units in the last place

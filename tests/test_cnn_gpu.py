@@ -164,13 +164,17 @@ def test_forward_random_weights_within_fp32_accumulation_bound():
     assert np.median(err / absum) < 1e-3
 
 
-@pytest.mark.parametrize("shape", [(32, 8, 8), (96, 8, 6), (32, 1, 1), (64, 3, 1)])
+@pytest.mark.parametrize("shape", [(32, 8, 8), (96, 8, 6), (32, 1, 1), (64, 3, 1),
+                                   (32, 24, 48), (64, 40, 20)])
 def test_gradients_match_the_oracle(shape):
     # (96, 8, 6): three 32-cell blocks per row (the weight-gradient kernel
     # takes two per step, so the second of the last pair is masked) and
     # fewer rows than workgroups (some sum nothing); (32, 1, 1) and
     # (64, 3, 1): one row or one plane, where every y or z shift wraps onto
-    # the cell itself
+    # the cell itself.  (32, 24, 48) and (64, 40, 20): 1152 and 800 mesh
+    # rows over the 512 weight-gradient workgroups, so each workgroup sums
+    # two or three rows and many of those runs cross from the last row of a
+    # plane to the first row of the next
     nx, ny, nz = shape
     _say(f"case: cnn gradients {nx}x{ny}x{nz} periodic")
     from paper_1812_07977_amd.learned import split_params
@@ -213,6 +217,97 @@ def test_gradients_match_the_oracle(shape):
     for name, gg, ref, sc in [("W1", got[0], dw1, aw1), ("b1", got[1], db1, ab1),
                               ("W2", got[2], dw2, aw2), ("b2", got[3], db2, ab2),
                               ("W3", got[4], dw3, aw3), ("b3", got[5], db3, ab3)]:
+        err = np.abs(gg - ref)
+        assert np.all(err <= tol * sc + 1e-30), (name, float(np.max(err / (sc + 1e-300))))
+        assert np.max(np.abs(ref)) > 0, name
+
+
+def _far_apart_cells(rng, n, count, min_sep, first=()):
+    """The cells `first` followed by random cells of a periodic n^3 mesh, count
+    in all, each pair more than min_sep cells apart along some axis
+    (Chebyshev distance, periodic)."""
+    def far(c, d):
+        return max(min(abs(a - b), n - abs(a - b)) for a, b in zip(c, d)) > min_sep
+    cells = list(first)
+    assert all(far(c, d) for q, c in enumerate(cells) for d in cells[:q])
+    while len(cells) < count:
+        c = tuple(int(v) for v in rng.integers(0, n, 3))
+        if all(far(c, d) for d in cells):
+            cells.append(c)
+    return cells
+
+
+def test_gradients_at_128_cubed_sparse_target_match_oracle_patches():
+    # The learned form's mesh size and launch configuration: 128^3 periodic,
+    # 16384 mesh rows, so each of the 512 weight-gradient workgroups sums 32
+    # rows, and the input-gradient convolutions (ReLU mask fused) march
+    # 8-plane chunks.  The target equals the network output except at K
+    # sampled cells, so the output gradient is zero elsewhere and every
+    # parameter gradient is the sum of the samples' contributions.  A
+    # sample's contribution depends only on the input within 3 cells (the
+    # hidden-layer gradients reach 2 cells out, the weights they multiply 1
+    # more), so the oracle evaluates the forward and backward pass on each
+    # sample's 7^3 periodic neighbourhood with only its centre's output
+    # gradient set.  Samples are more than 5 cells apart, so no two
+    # backward footprints meet and each BF16 rounding of a hidden gradient
+    # sees one sample's value, as on the GPU.
+    import torch
+    from paper_1812_07977_amd.learned import split_params
+    n = 128
+    K = 48
+    rng = np.random.default_rng(22)
+    flat = _dyadic_params(rng)
+    head = rng.integers(-8, 9, (5, n, n, n)) / 8.0
+    # the first two neighbourhoods wrap around the mesh on every axis / on two
+    cells = _far_apart_cells(rng, n, K, 5, first=[(0, 0, 0), (64, n - 1, 1)])
+    _say(f"case: cnn gradients 128^3 periodic, sparse target at {len(cells)} cells")
+    with _net((n, n, n)) as N:
+        N.set_params(flat)
+        U = _pair(head)
+        y = N.forward(U)
+        t = y.clone()
+        e = (rng.integers(1, 9, (len(cells), 5)) * rng.choice([-1, 1], (len(cells), 5)) / 8.0)
+        for (k, j, i), ev in zip(cells, e):
+            t[:, k, j, i] = y[:, k, j, i] - torch.from_numpy(ev.astype(np.float32)).cuda()
+        loss, g = N.gradients(U, t)
+        y_np = y.cpu().numpy()
+        t_np = t.cpu().numpy()
+    # the GPU's loss kernel: d = y - t in FP32, output gradient
+    # bf16(fp32(2 / N) d), N = 5 n^3
+    d = (y_np - t_np).astype(np.float32)
+    nz_d = np.count_nonzero(d)
+    assert 0 < nz_d <= 5 * len(cells)
+    scale = np.float32(2.0 / (5 * n ** 3))
+    assert loss == pytest.approx(float(np.sum(d.astype(np.float64) ** 2)) / (5 * n ** 3), rel=1e-12)
+    params = _params_from_flat(flat)
+    (w1, b1), (w2, b2), (w3, b3) = params
+    r = ocnn.bf16_round
+    sums = [np.zeros_like(a) for a in (w1, b1, w2, b2, w3, b3)]
+    abss = [np.zeros_like(a) for a in (w1, b1, w2, b2, w3, b3)]
+    P = ocnn.PERIODIC
+    for (k, j, i) in cells:
+        idx = [np.arange(c - 3, c + 4) % n for c in (k, j, i)]
+        x = head[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
+        _, (a1, h1, a2, h2) = _oracle_forward_bf16(x, params, P)
+        dy = np.zeros((5, 7, 7, 7))
+        dy[:, 3, 3, 3] = r(scale * d[:, k, j, i])
+        dw3, db3, dh2 = ocnn.conv3_backward(h2, r(w3), dy, P)
+        da2 = r(dh2 * (h2 > 0))
+        dw2, db2, dh1 = ocnn.conv3_backward(h1, r(w2), da2, P)
+        da1 = r(dh1 * (h1 > 0))
+        dw1, db1, _ = ocnn.conv3_backward(x, r(w1), da1, P)
+        aw3, ab3, _ = ocnn.conv3_backward(np.abs(h2), np.abs(r(w3)), np.abs(dy), P)
+        aw2, ab2, _ = ocnn.conv3_backward(np.abs(h1), np.abs(r(w2)), np.abs(da2), P)
+        aw1, ab1, _ = ocnn.conv3_backward(np.abs(x), np.abs(r(w1)), np.abs(da1), P)
+        for acc, v in zip(sums, (dw1, db1, dw2, db2, dw3, db3)):
+            acc += v
+        for acc, v in zip(abss, (aw1, ab1, aw2, ab2, aw3, ab3)):
+            acc += v
+    got = split_params(g.astype(np.float64))
+    # FP32 sums of the nonzero terms only (adding a zero is exact): at most
+    # 125 per sample (the first layer's gradient reaches 2 cells out)
+    tol = 1.5 * 125 * len(cells) * 2.0 ** -24
+    for name, gg, ref, sc in zip(["W1", "b1", "W2", "b2", "W3", "b3"], got, sums, abss):
         err = np.abs(gg - ref)
         assert np.all(err <= tol * sc + 1e-30), (name, float(np.max(err / (sc + 1e-300))))
         assert np.max(np.abs(ref)) > 0, name

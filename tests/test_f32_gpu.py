@@ -68,6 +68,13 @@ CASES = {
     "boosted_ragged": (lambda: wl.random_plane(40, 24, 20, seed=7, v=(0.7, -0.45, 0.3)),
                        "outflow", 30),
 }
+# Mach 3 along each axis and sign (both one-sided HLL branches), both
+# boundary kinds
+for _ax in range(3):
+    for _sg in (1, -1):
+        for _bc in ("outflow", "periodic"):
+            CASES[f"supersonic_{'xyz'[_ax]}{'+' if _sg > 0 else '-'}_{_bc}"] = (
+                (lambda a=_ax, s=_sg: wl.supersonic_contact(24, 20, 18, a, s)), _bc, 8)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))

@@ -22,6 +22,7 @@ ITERS = 6000
 TRAIN_PLANES = range(24)
 TRAIN_SINES = range(100, 106)
 HELD_OUT_PLANES = range(40, 46)
+VALIDATION_PLANES = range(60, 63)   # fit the blend factor: neither trained on nor evaluated
 MEAN_RATIO = 0.9   # mean corrected error below this fraction of the plain error
 MIN_IMPROVED = 5   # of the 6 held-out Riemann problems
 
@@ -58,7 +59,8 @@ def trained():
     tt = torch.tensor(tau, dtype=torch.float32, device="cuda")[:, None, None, None]
     targets = [r / tt for r in raw]
     hist = L.train(net, inputs, targets, ITERS, lr=3e-4, log_every=ITERS // 4)
-    alpha, errs = L.fit_blend(net, states[:3], STEPS)
+    del states
+    alpha, errs = L.fit_blend(net, [_fine("plane", s) for s in VALIDATION_PLANES], STEPS)
     _say(f"training loss {hist}; blend {alpha} from {errs}")
     del inputs, targets
     yield net, hist

@@ -100,6 +100,25 @@ def test_ragged_meshes_match_oracle(shape, bc):
     _assert_parity(out, ref)
 
 
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_supersonic_flow_takes_the_one_sided_hll_branches(axis, sign, bc):
+    # Mach 3 along one axis: on every face normal to it both signal speeds
+    # have the flow's sign, so the oracle returns F_L (sign +1) or F_R (sign
+    # -1) through its branches, while the GPU evaluates the clamped single
+    # expression with S_L or S_R clamped to 0
+    _say(f"case: supersonic contact axis {axis} sign {sign} {bc}, 8 steps, host dt")
+    U0 = wl.supersonic_contact(24, 20, 18, axis, sign)
+    ref, odt = oracle_run(U0, bc, 8)
+    out, gdt = gpu_run_host_dt(U0, bc, 8)
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
+    # the contact moved downstream: the first face column upstream of the
+    # jump changed, the state is not the initial one
+    assert not np.array_equal(out, U0)
+
+
 @pytest.mark.parametrize("launch", [(16, 0), (8, 0), (16, 1), (8, 3), (16, 64), (8, 7)])
 @pytest.mark.parametrize("boost", [(0.0, 0.0, 0.0), (0.9, -0.6, 0.4)])
 def test_launch_shapes_give_identical_results(launch, boost):

@@ -19,6 +19,8 @@ Section 4):
   sine_wave          smooth density wave advected at uniform v, p
   random_plane       seeded random discontinuity plane, rho and p ratios
                      log-uniform in [1, 100]
+  supersonic_contact a density jump carried by a uniform flow that is
+                     supersonic along one axis in every cell
   uniform            constant state
 """
 import math
@@ -142,6 +144,25 @@ def random_plane(nx, ny, nz, seed, gamma=GAMMA, v=(0.0, 0.0, 0.0)):
     rho = np.where(mask, 1.0, 1.0 / r_rho)
     p = np.where(mask, 1.0, 1.0 / r_p)
     return conserved(rho, *v, p, (nz, ny, nx), gamma)
+
+
+def supersonic_contact(nx, ny, nz, axis, sign, mach=3.0, gamma=GAMMA):
+    """A contact discontinuity in a uniform supersonic flow: p = 1, rho = 1
+    on the side a + 0.25 b + 0.15 c < 0.55 of a tilted plane (a the
+    coordinate along `axis`, b and c the other two in cyclic order) and 0.2
+    beyond it, velocity sign * mach * c_max along `axis` with c_max the sound
+    speed of the lighter gas.  Every face state a minmod reconstruction can
+    form lies between the two gases, so along `axis` both of a face's signal
+    speeds have the flow's sign."""
+    x, y, z = centres(nx, ny, nz)
+    c = [x, y, z]
+    a, b, cc = c[axis], c[(axis + 1) % 3], c[(axis + 2) % 3]
+    mask = np.broadcast_to(a + 0.25 * b + 0.15 * cc < 0.55, (nz, ny, nx))
+    rho = np.where(mask, 1.0, 0.2)
+    speed = sign * mach * math.sqrt(gamma * 1.0 / 0.2)
+    v = [0.0, 0.0, 0.0]
+    v[axis] = speed
+    return conserved(rho, *v, 1.0, (nz, ny, nx), gamma)
 
 
 def random_batch_dims(count, seed, lo=32, hi=160):
