@@ -291,7 +291,8 @@ def f32_error(U0, n, dts, U64):
     return l1, linf
 
 
-def learned_form(n=128, iters=8000, eval_steps=200, stride=10, eval_seeds=(99, 98, 97)):
+def learned_form(n=128, iters=8000, eval_steps=200, stride=10,
+                 eval_seeds=(99, 98, 97, 96, 95, 94, 93, 92)):
     """The learned-correction form on the coarse/fine pair n^3 / (2n)^3
     (periodic unit cubes): train the network on fine FP64 runs restricted
     2:1 (seeded random-plane Riemann problems and sine waves), then time, to
@@ -408,6 +409,10 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=10, eval_seeds=(99, 9
         "per_seed": [{k: r[k] for k in ("seed", "corr", "plain", "applied", "fallbacks")}
                      for r in per_seed],
         "mean_l1_ratio_corrected_over_plain": round(float(np.mean(ratios)), 4),
+        "worst_l1_ratio_corrected_over_plain": round(float(np.max(ratios)), 4),
+        "best_l1_ratio_corrected_over_plain": round(float(np.min(ratios)), 4),
+        "fraction_improved": round(float(np.mean([r < 1.0 for r in ratios])), 4),
+        "l1_ratio_per_seed": {str(r["seed"]): round(q, 4) for r, q in zip(per_seed, ratios)},
         "corrections_applied": first["applied"], "fallbacks": first["fallbacks"], "blend": alpha,
         "blend_fit_l1": {str(k): round(v, 5) for k, v in blend_errs.items()},
         "blend_fit_on": "random-plane Riemann problems, seeds 50-52 (validation)",

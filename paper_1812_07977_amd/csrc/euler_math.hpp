@@ -135,6 +135,16 @@ __device__ __forceinline__ bool cell_rate(const T u[NV], const Phys& k, double& 
 // the single expression with S_L clamped to <= 0 and S_R to >= 0, which is
 // the same function.
 //
+// The average is regrouped by side.  With w_L = S_R/(S_R - S_L),
+// w_R = -S_L/(S_R - S_L) and w_d = S_L S_R/(S_R - S_L), the flux is
+// w_L F_L + w_R F_R + w_d (U_R - U_L).  Every component of a physical flux
+// is the conserved component times the normal velocity, plus a pressure term
+// in the normal momentum and energy components, so each side contributes its
+// conserved state times a_L = w_L u_L - w_d (a_R = w_R u_R + w_d) plus
+// pressure terms; density times a_s (b_s) then carries the mass component
+// and, times a velocity, every momentum component.  The conserved momenta
+// and the physical fluxes are never formed.
+//
 // |v|^2 is summed as the normal component onto (first tangential^2 + second
 // tangential^2), with the tangential components in the order (y, z), (x, z),
 // (x, y) for AX = 0, 1, 2.  A face along x evaluated as AX = 1 with the x and
@@ -147,30 +157,28 @@ __device__ __forceinline__ void hll_flux(const R L[NV], const R Rs[NV], const Ph
     constexpr int T1 = (AX == 0) ? 2 : 1;    // tangential components
     constexpr int T2 = (AX == 2) ? 2 : 3;
     const R half = R(0.5);
-    // conserved face states
-    R mL1 = L[0] * L[1], mL2 = L[0] * L[2], mL3 = L[0] * L[3];
-    R mR1 = Rs[0] * Rs[1], mR2 = Rs[0] * Rs[2], mR3 = Rs[0] * Rs[3];
+    // total energies of the face states
     R v2L = fmaR(L[N], L[N], fmaR(L[T2], L[T2], L[T1] * L[T1]));
     R v2R = fmaR(Rs[N], Rs[N], fmaR(Rs[T2], Rs[T2], Rs[T1] * Rs[T1]));
     R EL = fmaR(L[4], k.inv_gm1, (half * L[0]) * v2L);
     R ER = fmaR(Rs[4], k.inv_gm1, (half * Rs[0]) * v2R);
-    const R uL[NV] = {L[0], mL1, mL2, mL3, EL};
-    const R uR[NV] = {Rs[0], mR1, mR2, mR3, ER};
-    // physical fluxes
+    // signal speeds and weights
     R unL = L[N], unR = Rs[N];
-    R fL[NV] = {uL[N], mL1 * unL, mL2 * unL, mL3 * unL, (EL + L[4]) * unL};
-    R fR[NV] = {uR[N], mR1 * unR, mR2 * unR, mR3 * unR, (ER + Rs[4]) * unR};
-    fL[N] = fmaR(uL[N], unL, L[4]);
-    fR[N] = fmaR(uR[N], unR, Rs[4]);
-    // signal speeds
     R cL = sound_speed(L[0], L[4], k);
     R cR = sound_speed(Rs[0], Rs[4], k);
     R sl = minR(minR(unL - cL, unR - cR), R(0));
     R sr = maxR(maxR(unL + cL, unR + cR), R(0));
     R inv = recip(sr - sl);
     R wl = sr * inv, wr = -sl * inv, wd = sl * wl;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = fmaR(wl, fL[v], fmaR(wr, fR[v], wd * (uR[v] - uL[v])));
+    // per-side factors
+    R wlu = wl * unL, wru = wr * unR;
+    R aL = wlu - wd, aR = wru + wd;
+    R bL = L[0] * aL, bR = Rs[0] * aR;
+    F[0] = bL + bR;
+    F[T1] = fmaR(L[T1], bL, Rs[T1] * bR);
+    F[T2] = fmaR(L[T2], bL, Rs[T2] * bR);
+    F[N] = fmaR(L[N], bL, fmaR(Rs[N], bR, fmaR(wl, L[4], wr * Rs[4])));
+    F[4] = fmaR(EL, aL, fmaR(ER, aR, fmaR(wlu, L[4], wru * Rs[4])));
 }
 
 // Flux through the face between cells b and c along axis AX, from the

@@ -14,11 +14,14 @@
 //     iteration ahead), the left face state of face k+1/2 and the z-flux of
 //     face k-1/2.  Every z-face flux is computed once.
 //   * In the plane, primitives of the tile plus a two-cell halo (a cross: the
-//     stencil never reads corners) are staged in LDS.  Thread (tx, ty)
-//     computes the x-face to its left and the y-face below it; one wave
-//     computes the TX + TY faces on the far edges, so every in-plane face is
-//     also computed once.  Face fluxes go to LDS, and the divergence reads the
-//     two faces of each cell back.
+//     stencil never reads corners) are staged in LDS.  Thread (tx, ty) limits
+//     its own cell along x and y once, keeps the right states of its low-side
+//     faces and passes the left states of its high-side faces to the next
+//     cells through the flux buffers; it then computes the x-face to its left
+//     and the y-face below it, and one wave computes the TX + TY faces on the
+//     far edges, so every in-plane slope and face is computed once.  Face
+//     fluxes go to LDS, and the divergence reads the two faces of each cell
+//     back.
 //   * Ghost cells are virtual: every index outside the mesh is mapped to the
 //     proper cell it copies (outflow) or wraps to (periodic) before loading,
 //     so arrays hold proper cells only and GhostExchange costs no pass.
