@@ -133,6 +133,35 @@ int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end,
                      double* dt_log);
 
 /*
+ * Allocation-free advance, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same computation as gs_fluid_create (with the same
+ * arguments and checks) + gs_fluid_set_time(t0) + gs_fluid_advance(U, nsteps,
+ * t_end, dt_log) with the default launch shape, giving bit-identical U and
+ * dt_log, but without a handle: the workspace (U(1), reduction partials,
+ * device words) is a 96 MiB array inside the library that each GPU it runs
+ * on holds until the process ends.  Calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   U: caller's device state, layout of dtype (FP32: the [head | comp] pair).
+ *   t_out, flags_out: optional device pointers (NULL: not written) receiving,
+ *     at the end of the queued work, the device time after the last step and
+ *     the non-physical flag word (bit 0 set if any state read held a
+ *     non-positive or non-finite density or pressure).
+ * Meshes whose workspace exceeds the array (more than 2,516,582 cells, FP64
+ * or FP32) are rejected with GS_ERR_ARG before any HIP call, as are the
+ * arguments gs_fluid_create or gs_fluid_advance would reject.  Asynchronous
+ * on `stream`; errors are reported by gs_fluid_last_error(NULL).  The array
+ * keeps the last call's contents, and every call on one GPU shares it: calls
+ * whose queued work overlaps on one GPU (two host threads, or two streams
+ * without ordering) race and give undefined results.
+ */
+int gs_fluid_advance_noalloc(int nx, int ny, int nz, double dx, double dy,
+                             double dz, double gamma, double cfl, int bc,
+                             int dtype, void* U, int nsteps, double t0,
+                             double t_end, double* dt_log, double* t_out,
+                             unsigned int* flags_out, void* stream);
+
+/*
  * Conserved totals: totals[f] = sum over proper cells of field f of U
  * (host array of 5 doubles), for the FP32 form of head - compensation.  FP64
  * with error-free (TwoSum) accumulation in a fixed order: deterministic, and

@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 
 __all__ = ["Fluid", "GSError", "NonPhysicalError", "OUTFLOW", "PERIODIC", "F64", "F32",
-           "stream_probe"]
+           "stream_probe", "advance_noalloc"]
 
 OUTFLOW = _lib.GS_BC_OUTFLOW
 PERIODIC = _lib.GS_BC_PERIODIC
@@ -249,3 +249,42 @@ def stream_probe(a, c, b=None, nontemporal=False, stream=None):
     _check(_lib.lib().gs_fluid_stream_probe(ctypes.c_void_p(a.data_ptr()), bp,
                                             ctypes.c_void_p(c.data_ptr()), int(a.numel()),
                                             1 if nontemporal else 0, _stream_ptr(stream)))
+
+
+def advance_noalloc(U, nsteps, spacing=None, gamma=1.4, cfl=0.5, bc="outflow", t0=0.0,
+                    t_end=0.0, dt_log=None, t_out=None, flags_out=None, stream=None):
+    """gs_fluid_advance_noalloc: nsteps device-dt RK2 steps of state U in
+    place with the library's own workspace (no device allocation, no handle).
+    U: float64 (5, nz, ny, nx) or float32 (2, 5, nz, ny, nx) contiguous GPU
+    tensor; dt_log (float64, >= nsteps), t_out (float64, >= 1) and flags_out
+    (int32, >= 1): optional GPU tensors written on the stream."""
+    import torch
+    if not isinstance(U, torch.Tensor) or not U.is_cuda or not U.is_contiguous():
+        raise TypeError("U must be a contiguous GPU tensor")
+    if U.dtype == torch.float64 and U.dim() == 4:
+        dtype = F64
+    elif U.dtype == torch.float32 and U.dim() == 5 and U.shape[0] == 2:
+        dtype = F32
+    else:
+        raise ValueError("U must be float64 (5, nz, ny, nx) or float32 (2, 5, nz, ny, nx)")
+    if U.shape[-4] != 5:
+        raise ValueError("U must hold 5 fields")
+    nz, ny, nx = (int(n) for n in U.shape[-3:])
+    if spacing is None:
+        h = 1.0 / max(nx, ny, nz)
+        spacing = (h, h, h)
+    if bc not in _BC_NAMES:
+        raise ValueError(f"unknown boundary kind {bc!r}")
+
+    def ptr(t, want, n, name):
+        if t is None:
+            return None
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be a contiguous {want} GPU tensor of >= {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    _check(_lib.lib().gs_fluid_advance_noalloc(
+        nx, ny, nz, *(float(s) for s in spacing), float(gamma), float(cfl), _BC_NAMES[bc], dtype,
+        ctypes.c_void_p(U.data_ptr()), int(nsteps), float(t0), float(t_end),
+        ptr(dt_log, torch.float64, nsteps, "dt_log"), ptr(t_out, torch.float64, 1, "t_out"),
+        ptr(flags_out, torch.int32, 1, "flags_out"), _stream_ptr(stream)))

@@ -36,6 +36,8 @@ SIGNATURES = [
     ("gs_fluid_dt", _I, [_VP, _VP, _PD]),
     ("gs_fluid_step", _I, [_VP, _VP, _D]),
     ("gs_fluid_advance", _I, [_VP, _VP, _I, _D, _VP]),
+    ("gs_fluid_advance_noalloc", _I, [_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _VP, _I, _D, _D,
+                                      _VP, _VP, _VP, _VP]),
     ("gs_fluid_totals", _I, [_VP, _VP, _PD]),
     ("gs_fluid_sync", _I, [_VP]),
     ("gs_fluid_get_time", _I, [_VP, _PD]),

@@ -37,6 +37,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -195,6 +196,26 @@ stream_probe_kernel(const probe_d2* __restrict__ a, const probe_d2* __restrict__
             else c[i] = r;
         }
     }
+}
+
+// Workspace of the allocation-free advance (gs_fluid_advance_noalloc): the
+// first-substep state (and the FP32 form's first increment), the reduction
+// partials and the device words of one solve, in one file-scope array that
+// every GPU the library runs on holds until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress returns on each
+// device.
+constexpr size_t NOALLOC_STATE_BYTES = size_t(96) << 20;
+constexpr size_t NOALLOC_PARTIAL_BYTES = size_t(RED_BLOCKS) * 2 * NV * sizeof(double);
+constexpr size_t NOALLOC_WORDS_BYTES = (sizeof(DevState) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_STATE_BYTES + NOALLOC_PARTIAL_BYTES + NOALLOC_WORDS_BYTES;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Copies the device time and the non-physical flag of a solve to caller
+// memory (either pointer may be null).
+__global__ void report_kernel(const DevState* st, int parity, double* t_out, unsigned int* flags_out)
+{
+    if (t_out) *t_out = st->t[parity];
+    if (flags_out) *flags_out = st->flags;
 }
 
 }  // namespace gs
@@ -544,22 +565,13 @@ hipError_t advance_t(gs_fluid* h, T* u, int nsteps, double t_end, double* dt_log
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype)
+// Argument checks shared by gs_fluid_create and gs_fluid_advance_noalloc;
+// no HIP call.
+int check_problem(int nx, int ny, int nz, double dx, double dy, double dz, double gamma,
+                  double cfl, int bc, int dtype)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || (dtype != GS_F64 && dtype != GS_F32)) return -1;
-    long long ncell = (long long)nx * ny * nz;
-    return state_work_bytes(ncell, dtype) + RED_BLOCKS * 2 * NV * (long long)sizeof(double) +
-           (long long)sizeof(DevState);
-}
-
-int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, double gamma,
-                    double cfl, int bc, int dtype, void* stream, gs_fluid** out)
-{
-    g_create_error.clear();
-    if (!out) return fail(nullptr, GS_ERR_ARG, "out is NULL");
-    *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return fail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
     if ((long long)nx * ny > (1LL << 30) ||
         (long long)nx * ny * nz * NV > (1LL << 40))
@@ -574,18 +586,27 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
         return fail(nullptr, GS_ERR_ARG, "unknown boundary kind");
     if (dtype != GS_F64 && dtype != GS_F32)
         return fail(nullptr, GS_ERR_ARG, "unknown dtype (GS_F64 or GS_F32)");
+    return GS_OK;
+}
 
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
+// The current device, checked to be a gfx950.
+int current_gfx950(int* dev)
+{
+    hipError_t e = hipGetDevice(dev);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
     hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, dev);
+    e = hipGetDeviceProperties(&prop, *dev);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceProperties");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, GS_ERR_HIP,
                     std::string("built for gfx950, device is ") + prop.gcnArchName);
+    return GS_OK;
+}
 
-    gs_fluid* h = new gs_fluid();
+// Handle fields of a problem; no allocation, no HIP call.
+void init_handle(gs_fluid* h, int nx, int ny, int nz, double dx, double dy, double dz,
+                 double gamma, double cfl, int bc, int dtype, int dev, void* stream)
+{
     h->nx = nx;
     h->ny = ny;
     h->nz = nz;
@@ -607,6 +628,63 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
     h->tile_y = 0;
     h->chunk_z = 0;
     h->profile = false;
+}
+
+// Device address of the allocation-free workspace on each device, looked up
+// once per device with that device current.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[NOALLOC_MAX_DEVICES];
+
+int scratch_address(unsigned char** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(nullptr, GS_ERR_HIP, "device index beyond the allocation-free table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int r = current_gfx950(&dev);
+        if (r != GS_OK) return r;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(nullptr, GS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch[dev];
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+long long gs_fluid_workspace_bytes(int nx, int ny, int nz, int dtype)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || (dtype != GS_F64 && dtype != GS_F32)) return -1;
+    long long ncell = (long long)nx * ny * nz;
+    return state_work_bytes(ncell, dtype) + RED_BLOCKS * 2 * NV * (long long)sizeof(double) +
+           (long long)sizeof(DevState);
+}
+
+int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz, double gamma,
+                    double cfl, int bc, int dtype, void* stream, gs_fluid** out)
+{
+    g_create_error.clear();
+    if (!out) return fail(nullptr, GS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int r0 = check_problem(nx, ny, nz, dx, dy, dz, gamma, cfl, bc, dtype);
+    if (r0 != GS_OK) return r0;
+
+    int dev = 0;
+    r0 = current_gfx950(&dev);
+    if (r0 != GS_OK) return r0;
+    hipError_t e;
+
+    gs_fluid* h = new gs_fluid();
+    init_handle(h, nx, ny, nz, dx, dy, dz, gamma, cfl, bc, dtype, dev, stream);
 
     const size_t state_bytes = (size_t)state_work_bytes((long long)nx * ny * nz, dtype);
     if ((e = hipMalloc(&h->U1, state_bytes)) != hipSuccess ||
@@ -667,6 +745,56 @@ int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end, double* dt_
                                         : advance_t(h, (double*)U, nsteps, t_end, dt_log);
     if (e != hipSuccess) return hip_fail(h, e, "advance launch");
     return GS_OK;
+}
+
+int gs_fluid_advance_noalloc(int nx, int ny, int nz, double dx, double dy, double dz,
+                             double gamma, double cfl, int bc, int dtype, void* U, int nsteps,
+                             double t0, double t_end, double* dt_log, double* t_out,
+                             unsigned int* flags_out, void* stream)
+{
+    g_create_error.clear();
+    int r = check_problem(nx, ny, nz, dx, dy, dz, gamma, cfl, bc, dtype);
+    if (r != GS_OK) return r;
+    const long long ncell = (long long)nx * ny * nz;
+    if (state_work_bytes(ncell, dtype) > (long long)NOALLOC_STATE_BYTES)
+        return fail(nullptr, GS_ERR_ARG,
+                    "mesh too large for the allocation-free entry point (its workspace holds "
+                    "96 MiB: 2,516,582 cells)");
+    if (!U || !aligned_to(U, elem_size(dtype)))
+        return fail(nullptr, GS_ERR_ARG, "U is NULL or not aligned to its element size");
+    if (nsteps < 0) return fail(nullptr, GS_ERR_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(t0)) return fail(nullptr, GS_ERR_ARG, "t0 must be finite");
+    if (!std::isfinite(t_end) || t_end < 0.0)
+        return fail(nullptr, GS_ERR_ARG, "t_end must be finite and >= 0");
+    if ((dt_log && !aligned8(dt_log)) || (t_out && !aligned8(t_out)) ||
+        (flags_out && !aligned_to(flags_out, 4)))
+        return fail(nullptr, GS_ERR_ARG, "dt_log, t_out or flags_out misaligned");
+
+    unsigned char* ws = nullptr;
+    r = scratch_address(&ws);
+    if (r != GS_OK) return r;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+
+    // a handle on the stack whose workspace is the device array
+    gs_fluid h;
+    init_handle(&h, nx, ny, nz, dx, dy, dz, gamma, cfl, bc, dtype, dev, stream);
+    h.U1 = ws;
+    h.partial = (double*)(ws + NOALLOC_STATE_BYTES);
+    h.st = (DevState*)(ws + NOALLOC_STATE_BYTES + NOALLOC_PARTIAL_BYTES);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h.stream, h.st);
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(1), 0, h.stream, h.st, 0, t0);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = (dtype == GS_F32) ? advance_t(&h, (float*)U, nsteps, t_end, dt_log)
+                              : advance_t(&h, (double*)U, nsteps, t_end, dt_log);
+    if (e == hipSuccess && (t_out || flags_out)) {
+        hipLaunchKernelGGL(report_kernel, dim3(1), dim3(1), 0, h.stream, h.st, h.parity, t_out,
+                           flags_out);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? GS_OK : hip_fail(nullptr, e, "allocation-free advance launch");
 }
 
 int gs_fluid_totals(gs_fluid* h, const void* U, double* totals)

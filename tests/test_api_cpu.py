@@ -94,6 +94,47 @@ def test_null_handle_calls_are_argument_errors():
     assert L.gs_fluid_last_error(None) is not None
 
 
+NA_OK = dict(G_OK, U=4096, nsteps=1, t0=0.0, t_end=0.0, dt_log=None, t_out=None, flags_out=None)
+
+
+def _noalloc(**over):
+    a = dict(NA_OK)
+    a.update(over)
+    return _lib().gs_fluid_advance_noalloc(
+        a["nx"], a["ny"], a["nz"], a["dx"], a["dy"], a["dz"], a["gamma"], a["cfl"], a["bc"],
+        a["dtype"], a["U"], a["nsteps"], a["t0"], a["t_end"], a["dt_log"], a["t_out"],
+        a["flags_out"], None)
+
+
+@pytest.mark.parametrize("over", [
+    dict(nx=0), dict(dz=math.nan), dict(gamma=1.0), dict(cfl=1.5), dict(bc=2), dict(dtype=3),
+    dict(U=None), dict(U=4097), dict(nsteps=-1), dict(t0=math.inf), dict(t_end=-1.0),
+    dict(t_end=math.nan), dict(dt_log=4100), dict(t_out=4), dict(flags_out=2),
+    # workspace above the 96 MiB array: FP64 and FP32 both need 40 B per cell
+    dict(nx=160, ny=128, nz=123), dict(nx=160, ny=128, nz=123, dtype=1),
+])
+def test_noalloc_rejects_bad_arguments_before_any_hip_call(over):
+    # the state pointer is a host integer that is never dereferenced: every
+    # case must fail in validation
+    assert _noalloc(**over) == lib_mod.GS_ERR_ARG
+    assert _lib().gs_fluid_last_error(None).decode()
+
+
+def test_noalloc_size_limit_is_the_stated_cell_count():
+    # 2,516,582 cells fit the 96 MiB workspace at 40 B per cell; one more does not
+    assert 2516582 * 40 <= 96 << 20 < 2516583 * 40
+    st = _noalloc(nx=2516583, ny=1, nz=1)
+    assert st == lib_mod.GS_ERR_ARG
+    assert "too large" in _lib().gs_fluid_last_error(None).decode()
+
+
+def test_noalloc_valid_call_without_gpu_is_a_hip_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _noalloc(nx=2516582, ny=1, nz=1) == lib_mod.GS_ERR_HIP
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_workspace_bytes(dtype):
     L = _lib()
