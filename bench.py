@@ -23,8 +23,9 @@ fraction of the HBM peak, and the CPU oracle timed on a bounded sample on
 the host cores (all threads; then one eighth of them and one, on a smaller
 sample).  After the reported block of steps, four more blocks of the same
 length give the spread of the rate (reported with their median), and 20
-steps of the host-synchronised path (gs_fluid_dt, then gs_fluid_step) give
-its rate.  Under "cases" the random-plane Riemann case and the smooth case
+steps of the host-synchronised path (gs_fluid_dt, then gs_fluid_step) and
+20 of the host-synchronised path on the step's fused max (gs_fluid_step_dt)
+give their rates.  Under "cases" the random-plane Riemann case and the smooth case
 at 512^3 and 256^3 are timed the same way, FP64 and FP32 (with the FP32
 error per field on the 512^3 Riemann case).  Under "forms" the FP32 form is
 timed the same way on the headline input, with its speedup over FP64 and
@@ -198,6 +199,16 @@ def timed_run(U0, n, dtype, steps, warmup, tile_y, chunk_z, repeats=1, host_step
         F.sync()
         extra["host_dt_ms"] = t0.elapsed_time(t1)
         extra["host_steps"] = host_steps
+        # the same loop on the max each step fuses into its second substep
+        # (gs_fluid_step_dt): one 8-byte read-back per step, no reduction
+        dt = F.dt(S)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(host_steps):
+            dt = F.step_dt(S, dt)
+        t1.record(stream)
+        F.sync()
+        extra["host_dt_last_ms"] = t0.elapsed_time(t1)
     F.close()
     return {"total_ms": total_ms, "per_kernel": per_kernel, "t_sim": t_sim, **extra}, dts, result
 
@@ -289,6 +300,80 @@ def f32_error(U0, n, dts, U64):
         l1.append(float(f"{float(d.sum()) / s1:.3e}"))
         linf.append(float(f"{float(d.max()) / sinf:.3e}"))
     return l1, linf
+
+
+def equal_cost_plain(net, alpha, seed, eval_steps, n):
+    """The corrected n^3 solve against a plain FP32 solve on a finer mesh of
+    about the same cost, both measured against one finer reference: the
+    held-out problem `seed` is sampled on a (3n)^3 mesh, solved there in
+    FP64, and its conservative averages over 3^3 and 2^3 cells give the
+    n^3 and (3n/2)^3 references (and the initial states of the coarse
+    solves).  The n^3 solves take the plain n^3 run's own CFL steps; the
+    (3n/2)^3 solve takes its own CFL steps to the same end time."""
+    import numpy as np
+    import torch
+    import torch.nn.functional as tf
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    r, m = 3 * n, 3 * n // 2
+    U0 = torch.from_numpy(wl.random_plane(r, r, r, seed=seed)).cuda()
+
+    def avg(U, k):
+        return tf.avg_pool3d(U.unsqueeze(0), k).squeeze(0).contiguous()
+
+    def l1(ref, S, F):
+        d = (F.to_f64(S) - ref).abs().sum(dim=(1, 2, 3))
+        a = ref.abs().sum(dim=(1, 2, 3))
+        return [round(float(d[list(g)].sum() / a[list(g)].sum()), 5) for g in ((0,), (1, 2, 3), (4,))]
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev0.record()
+        fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    Cn = Fluid((n,) * 3, bc="periodic", dtype="f32")
+    plain = Cn.state_from(avg(U0, 3))
+    dts = []
+    for _ in range(eval_steps):
+        dt = Cn.dt(plain)
+        dts.append(dt)
+        Cn.step(plain, dt)
+    T = float(sum(dts))
+    corr = Cn.state_from(avg(U0, 3))
+
+    def corrected():
+        for dt in dts:
+            Cn.step(corr, dt)
+            if alpha > 0:
+                net.correct(corr)
+    ms_corr = timed(corrected)
+    Cm = Fluid((m,) * 3, bc="periodic", dtype="f32")
+    fine_m = Cm.state_from(avg(U0, 2))
+    log = torch.zeros(4 * eval_steps, dtype=torch.float64, device="cuda")
+    Cm.time = 0.0
+    ms_m = timed(lambda: Cm.advance(fine_m, 4 * eval_steps, T, log))
+    steps_m = int((log > 0).sum())
+    Fr = Fluid((r,) * 3, bc="periodic", dtype="f64")
+    Ur = U0.clone()
+    del U0
+    Fr.time = 0.0
+    Fr.advance(Ur, 8 * eval_steps, T)
+    Fr.sync()
+    out = {
+        "reference": f"{r}^3 FP64 solve of seed {seed} to t = {T:.5f}, averaged over 3^3 and 2^3 cells",
+        f"corrected_{n}": {"ms": round(ms_corr, 2), "l1": l1(avg(Ur, 3), corr, Cn)},
+        f"plain_{n}": {"l1": l1(avg(Ur, 3), plain, Cn)},
+        f"plain_{m}": {"ms": round(ms_m, 2), "steps": steps_m, "l1": l1(avg(Ur, 2), fine_m, Cm)},
+        "l1_fields": ["rho", "momentum (all components)", "E"],
+    }
+    for F in (Cn, Cm, Fr):
+        F.close()
+    return out
 
 
 def learned_form(n=128, iters=8000, eval_steps=200, stride=10,
@@ -391,6 +476,7 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=10,
         del U0, Uf, plain, corr
     Ff.close()
     Cp.close()
+    equal_cost = equal_cost_plain(net, alpha, eval_seeds[0], eval_steps, n)
     net.close()
     first = per_seed[0]
     ratios = [float(np.mean(r["corr"]) / np.mean(r["plain"])) for r in per_seed]
@@ -416,6 +502,7 @@ def learned_form(n=128, iters=8000, eval_steps=200, stride=10,
         "corrections_applied": first["applied"], "fallbacks": first["fallbacks"], "blend": alpha,
         "blend_fit_l1": {str(k): round(v, 5) for k, v in blend_errs.items()},
         "blend_fit_on": "random-plane Riemann problems, seeds 50-52 (validation)",
+        "equal_cost": equal_cost,
         "training": f"{iters} Adam steps on 16 trajectories x {eval_steps // stride} states "
                     f"(every {stride}th of {eval_steps} steps; {f}^3 FP64 restricted), "
                     f"{t_train:.1f} s incl. data",
@@ -639,6 +726,11 @@ def main():
                     "ms_per_step": r64["host_dt_ms"] / r64["host_steps"],
                     "note": "gs_fluid_dt (reduction + 8-byte read-back + sync) then gs_fluid_step, "
                             "240 B/cell-update"},
+        "host_dt_last": {"value": cells * r64["host_steps"] / (r64["host_dt_last_ms"] / 1e3),
+                         "unit": "cell-updates/s", "steps": r64["host_steps"],
+                         "ms_per_step": r64["host_dt_last_ms"] / r64["host_steps"],
+                         "note": "gs_fluid_step_dt (the step with its fused max, then an 8-byte "
+                                 "read-back + sync, no reduction), 200 B/cell-update"},
         "hbm_ceiling_gbs": ceil,
         "roofline": roof,
         "alu": alu,

@@ -34,8 +34,10 @@ typedef struct gs_batch gs_batch;
 /*
  * A batch of count problems: dims is a host array [count][3] of (nx, ny, nz)
  * (each >= 1), states a host array of count device pointers (aligned to 16
- * bytes).  Allocates the workspaces of all problems (one state of the dtype
- * each, FP32: with the first increment) and the per-problem device words.
+ * bytes).  Allocates, per problem, a workspace (one state of the dtype, FP32:
+ * with the first increment) and the per-problem device words; for FP64, where
+ * nx is not a multiple of 16, the workspace and a working copy of the state
+ * have rows padded to whole 128-byte lines (nx rounded up to 16 doubles).
  */
 int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc, int dtype,
                     void* const* states, void* stream, gs_batch** out);
@@ -61,8 +63,12 @@ int gs_batch_autotune(gs_batch* h, const char* cache_path, int* tile_y, int* chu
  * condition of its own state), clipped to t_end if t_end > 0 (problems at
  * or past t_end stay unchanged).  use_graph != 0: each step is one replay
  * of a captured graph of the two substep launches; 0: the same launches
- * issued directly.  Before the first step, one reduction pass per problem.
- * No host wait.
+ * issued directly.  Before the first step, one reduction pass per problem
+ * and (FP64 with padded rows) one launch that copies the caller states into
+ * the working copies; after the last, one launch that copies them back (so
+ * every tile row of the steps lies on whole cache lines).  The caller's
+ * states must not be changed while the call's work is queued.  No host
+ * wait.
  */
 int gs_batch_advance(gs_batch* h, int nsteps, double t_end, int use_graph);
 

@@ -47,8 +47,9 @@
  *
  * Streams and synchronisation.  Every call queues work on the handle's
  * stream (hipStream_t, NULL = the legacy default stream) and returns without
- * waiting, except gs_fluid_dt, gs_fluid_totals, gs_fluid_sync,
- * gs_fluid_get_time and gs_fluid_kernel_ms, which wait for the stream.  A handle is not
+ * waiting, except gs_fluid_dt, gs_fluid_dt_last, gs_fluid_step_dt,
+ * gs_fluid_totals, gs_fluid_sync, gs_fluid_get_time and gs_fluid_kernel_ms,
+ * which wait for the stream.  A handle is not
  * thread-safe: use one handle per stream.
  *
  * Errors.  Every int-returning call returns GS_OK or a negative status;
@@ -112,12 +113,35 @@ int gs_fluid_create(int nx, int ny, int nz, double dx, double dy, double dz,
 int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out);
 
 /*
+ * ComputeTimeStep (Algorithm 1) without a reduction pass: *dt_out = cfl /
+ * the max signal rate of the state that the handle's last gs_fluid_advance
+ * or gs_fluid_step_dt wrote, which the second substep of its last step
+ * computed while writing it (the max over cells is exact, so the result
+ * equals gs_fluid_dt's on that unchanged state bit for bit).  Waits for the
+ * stream.  GS_ERR_STATE if the last state written came from gs_fluid_step,
+ * or none since the handle was created or its time was set; a caller that
+ * modifies the state itself afterwards must use gs_fluid_dt instead.
+ * Non-physical states are reported as by gs_fluid_dt.
+ */
+int gs_fluid_dt_last(gs_fluid* h, double* dt_out);
+
+/*
  * One RK2 step (Algorithm 1, both substeps) of size dt (finite, > 0): U is
  * read as U(n) and overwritten in place with U(n+1).  Two kernel launches on
  * the stream; no host synchronisation.  The handle's device time advances by
  * dt.
  */
 int gs_fluid_step(gs_fluid* h, void* U, double dt);
+
+/*
+ * The host-synchronised loop of Algorithm 1 in one call: gs_fluid_step
+ * whose second substep also takes the max signal rate of U(n+1) while
+ * writing it, then gs_fluid_dt_last: waits and sets *dt_next to the CFL
+ * time step of U(n+1), with no reduction pass (200 instead of 240 bytes of
+ * HBM traffic per cell and step).  Errors as gs_fluid_step and
+ * gs_fluid_dt_last.
+ */
+int gs_fluid_step_dt(gs_fluid* h, void* U, double dt, double* dt_next);
 
 /*
  * nsteps RK2 steps with the time step computed on the device: before the

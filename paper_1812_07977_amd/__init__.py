@@ -145,10 +145,27 @@ class Fluid:
         _check(_lib.lib().gs_fluid_dt(h, self._state_ptr(U), ctypes.byref(out)), h)
         return out.value
 
+    def dt_last(self):
+        """CFL time step of the state the last advance or step_dt wrote, from
+        the max its last step computed while writing it (no reduction;
+        waits)."""
+        out = ctypes.c_double()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_dt_last(h, ctypes.byref(out)), h)
+        return out.value
+
     def step(self, U, dt):
         """One RK2 step of size dt, in place (asynchronous)."""
         h = self._handle()
         _check(_lib.lib().gs_fluid_step(h, self._state_ptr(U), float(dt)), h)
+
+    def step_dt(self, U, dt):
+        """One RK2 step of size dt in place, then the CFL time step of the
+        new state from the max the step took while writing it (waits)."""
+        out = ctypes.c_double()
+        h = self._handle()
+        _check(_lib.lib().gs_fluid_step_dt(h, self._state_ptr(U), float(dt), ctypes.byref(out)), h)
+        return out.value
 
     def advance(self, U, nsteps, t_end=0.0, dt_log=None):
         """nsteps RK2 steps with device-computed dt (asynchronous).  dt_log:

@@ -34,7 +34,9 @@ _LL = ctypes.c_longlong
 SIGNATURES = [
     ("gs_fluid_create", _I, [_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _VP, ctypes.POINTER(_VP)]),
     ("gs_fluid_dt", _I, [_VP, _VP, _PD]),
+    ("gs_fluid_dt_last", _I, [_VP, _PD]),
     ("gs_fluid_step", _I, [_VP, _VP, _D]),
+    ("gs_fluid_step_dt", _I, [_VP, _VP, _D, _PD]),
     ("gs_fluid_advance", _I, [_VP, _VP, _I, _D, _VP]),
     ("gs_fluid_advance_noalloc", _I, [_I, _I, _I, _D, _D, _D, _D, _D, _I, _I, _VP, _I, _D, _D,
                                       _VP, _VP, _VP, _VP]),

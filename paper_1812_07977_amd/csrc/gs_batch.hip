@@ -30,8 +30,11 @@ struct BatchInst {
     Geom g;              // mesh and tiling (band unused)
     Phys kd;             // FP64 constants, with this problem's cell widths
     PhysT<float> kf;     // the same rounded to FP32
-    void* U;             // caller state (FP32 form: head, then compensation)
-    void* U1;            // workspace: U(1) (FP32 form: then dU(U(n)))
+    void* U;             // the state the steps advance: the batch's row-padded
+                         // working copy, or the caller's state where rows are
+                         // not padded (FP32 form: head, then compensation)
+    void* U1;            // workspace: U(1) (FP32 form: then dU(U(n))), padded
+    void* Uc;            // the caller's state, rows of nx cells
     DevState* st;        // this problem's device words
     int item0;           // first work item (tile, z-chunk) of this problem
     int items;
@@ -56,10 +59,9 @@ __device__ __forceinline__ P* global_ptr(const void* p)
 
 // Waves per SIMD of the batched kernels: three (at most 168 VGPRs), except
 // FP64 32 x 8 tiles, whose LDS (57 KiB per workgroup) admits two workgroups
-// per CU.  This source is compiled with the default scheduler, which fits
-// the FP64 16 x 16 body in the three-wave budget without spills (the
-// iterative ILP scheduler of the single-problem kernels does not, for this
-// loop).
+// per CU.  Under the compiler's default scheduler the FP64 16 x 16 body
+// fits the three-wave budget without spills (under the iterative ILP
+// scheduler the item loop took about 210 VGPRs).
 template <typename T, int TY>
 struct BatchOcc {
     static constexpr int waves = (sizeof(T) == 8 && TY == 8) ? 2 : 3;
@@ -191,6 +193,38 @@ __global__ void clear_words_kernel(unsigned int* __restrict__ w, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
 }
 
+// Copies every problem's state between the caller's layout (rows of nx
+// cells) and the batch's padded one (rows of g.pitch cells, each row
+// starting on a 128-byte line), one wave per row: IN copies caller ->
+// padded, else padded -> caller.  arrays = fields of a state (5; the FP32
+// form's pair 10).  Workgroup (p, s) walks rows s, s + gridDim.y, ... of
+// problem p; the padding cells are never read by the stage kernels.
+template <typename T, bool IN>
+__global__ void __launch_bounds__(256)
+copy_rows_kernel(const BatchInst* __restrict__ insts, int arrays)
+{
+    const BatchInst& I = insts[blockIdx.x];
+    if (I.U == I.Uc) return;  // steps run on the caller's state itself
+    const int nx = I.g.nx, ny = I.g.ny, nz = I.g.nz;
+    const long long rows = (long long)arrays * nz * ny;
+    const long long dense_field = (long long)nx * ny * nz;
+    T* pad = global_ptr<T>(I.U);
+    T* den = global_ptr<T>(I.Uc);
+    const int lane = threadIdx.x & 63;
+    for (long long r = (long long)blockIdx.y * 4 + (threadIdx.x >> 6); r < rows;
+         r += (long long)gridDim.y * 4) {
+        const long long a = r / ((long long)nz * ny);
+        const long long kj = r - a * nz * ny;
+        const long long k = kj / ny, j = kj - k * ny;
+        T* d = den + a * dense_field + (k * ny + j) * nx;
+        T* q = pad + a * I.g.field + k * I.g.plane + j * I.g.pitch;
+        for (int i = lane; i < nx; i += 64) {
+            if (IN) q[i] = d[i];
+            else d[i] = q[i];
+        }
+    }
+}
+
 }  // namespace gs
 
 // ===========================================================================
@@ -213,8 +247,10 @@ struct gs_batch {
     double gamma, cfl;
     std::vector<std::array<int, 3>> dims;
     std::vector<void*> states;
-    void* pool;                 // workspaces of all problems
-    std::vector<size_t> pool_off;
+    void* pool;                 // workspaces and padded states of all problems
+    std::vector<size_t> pool_off;   // workspace U(1) of problem i
+    std::vector<void*> padded;      // working copy of problem i's state with
+                                    // padded rows (null: rows not padded)
     DevState* st;               // count blocks of device words
     DevState* tune_st;          // device words for autotuning runs
     DevState* host_st;          // pinned mirror of st
@@ -268,8 +304,29 @@ Phys batch_phys64(const gs_batch* h, int i)
 
 // Per-problem geometry, constants and item ranges for the current launch
 // shape, with states `states` and device words `st`.
-std::vector<BatchInst> batch_table(const gs_batch* h, const std::vector<void*>& states, DevState* st,
-                                   int* total)
+// Row pitch of the batch's arrays.  FP64: rows padded to whole 128-byte
+// lines (16 doubles), so that every 16-wide tile row is one line (the
+// 64-problem batch measured 3% faster, copies included); FP32: the caller's
+// rows as they are (padding its pairs measured 6% slower).
+int batch_pitch(const gs_batch* h, int nx)
+{
+    if (h->dtype == GS_F32) return nx;
+    const int per_line = 128 / (int)h->esize;
+    return (nx + per_line - 1) / per_line * per_line;
+}
+
+// Elements of one padded array of problem i.
+long long padded_field(const gs_batch* h, int i)
+{
+    return (long long)batch_pitch(h, h->dims[i][0]) * h->dims[i][1] * h->dims[i][2];
+}
+
+// Fields in a state (the FP32 form's pair: head and compensation) and in a
+// workspace (FP32: U(1) and the first increment).
+int state_arrays(const gs_batch* h) { return h->dtype == GS_F32 ? 2 * NV : NV; }
+
+std::vector<BatchInst> batch_table(const gs_batch* h, const std::vector<void*>& states,
+                                   const std::vector<void*>& padded, DevState* st, int* total)
 {
     const int ty = batch_tile_y(h), tx = 256 / ty;
     std::vector<BatchInst> v(h->count);
@@ -283,8 +340,9 @@ std::vector<BatchInst> batch_table(const gs_batch* h, const std::vector<void*>& 
         g.ny = ny;
         g.nz = nz;
         g.periodic = h->bc == GS_BC_PERIODIC;
-        g.plane = nx * ny;
-        g.field = (long long)nx * ny * nz;
+        g.pitch = batch_pitch(h, nx);
+        g.plane = g.pitch * ny;
+        g.field = (long long)g.pitch * ny * nz;
         g.ntx = (nx + tx - 1) / tx;
         g.nty = (ny + ty - 1) / ty;
         const int ntile = g.ntx * g.nty;
@@ -308,8 +366,9 @@ std::vector<BatchInst> batch_table(const gs_batch* h, const std::vector<void*>& 
         I.kf.inv_gm1 = (float)k.inv_gm1;
         for (int d = 0; d < 3; ++d) I.kf.inv_h[d] = (float)k.inv_h[d];
         I.kf.cfl = (float)k.cfl;
-        I.U = states[i];
+        I.U = padded[i] ? padded[i] : states[i];
         I.U1 = (char*)h->pool + h->pool_off[i];
+        I.Uc = states[i];
         I.st = st + i;
         I.item0 = item;
         I.items = ntile * g.nchunk;
@@ -338,6 +397,21 @@ hipError_t batch_step(gs_batch* h, const BatchInst* table, int total, int parity
                    : batch_launch_t<double, 32, 8>(h, table, total, parity, t_end);
     return f32 ? batch_launch_t<float, 16, 16>(h, table, total, parity, t_end)
                : batch_launch_t<double, 16, 16>(h, table, total, parity, t_end);
+}
+
+// caller states <-> padded copies of every problem of `table`
+hipError_t batch_copy(gs_batch* h, const BatchInst* table, bool in)
+{
+    const dim3 grid(h->count, 64), block(256);
+    const int arrays = state_arrays(h);
+    if (h->dtype == GS_F32) {
+        if (in) hipLaunchKernelGGL((copy_rows_kernel<float, true>), grid, block, 0, h->stream, table, arrays);
+        else hipLaunchKernelGGL((copy_rows_kernel<float, false>), grid, block, 0, h->stream, table, arrays);
+    } else {
+        if (in) hipLaunchKernelGGL((copy_rows_kernel<double, true>), grid, block, 0, h->stream, table, arrays);
+        else hipLaunchKernelGGL((copy_rows_kernel<double, false>), grid, block, 0, h->stream, table, arrays);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int TX, int TY, int STAGE, bool RATE>
@@ -387,7 +461,7 @@ void drop_graphs(gs_batch* h)
 int rebuild_table(gs_batch* h)
 {
     int total = 0;
-    std::vector<BatchInst> t = batch_table(h, h->states, h->st, &total);
+    std::vector<BatchInst> t = batch_table(h, h->states, h->padded, h->st, &total);
     hipError_t e = hipMemcpy(h->insts_dev, t.data(), sizeof(BatchInst) * h->count, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bhip(h, e, "batch table upload");
     h->total_items = total;
@@ -507,11 +581,16 @@ int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc
     h->dims.resize(count);
     h->states.assign(states, states + count);
     size_t off = 0;
+    std::vector<size_t> pad_off(count);
     for (int i = 0; i < count; ++i) {
         h->dims[i] = {dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]};
+        // workspace and, where the rows are padded, a working copy of the
+        // state: state_arrays arrays each
+        const size_t bytes = (size_t)state_arrays(h) * padded_field(h, i) * h->esize;
         h->pool_off.push_back(off);
-        const long long ncell = (long long)dims[3 * i] * dims[3 * i + 1] * dims[3 * i + 2];
-        off += ((size_t)state_work_bytes(ncell, dtype) + 255) / 256 * 256;
+        off += (bytes + 255) / 256 * 256;
+        pad_off[i] = off;
+        if (batch_pitch(h, dims[3 * i]) != dims[3 * i]) off += (bytes + 255) / 256 * 256;
     }
     h->user_stream = (hipStream_t)stream;
     h->exec[0] = h->exec[1] = nullptr;
@@ -531,6 +610,9 @@ int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc
         gs_batch_destroy(h);
         return r;
     }
+    for (int i = 0; i < count; ++i)
+        h->padded.push_back(batch_pitch(h, h->dims[i][0]) != h->dims[i][0] ? (char*)h->pool + pad_off[i]
+                                                                          : nullptr);
     for (int i = 0; i < count; ++i) {
         hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st + i);
         hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, h->stream, h->tune_st + i);
@@ -571,6 +653,7 @@ int gs_batch_advance(gs_batch* h, int nsteps, double t_end, int use_graph)
     hipError_t e = hipEventRecord(h->ev_in, h->user_stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_in, 0);
     if (e == hipSuccess) e = batch_rates(h, h->states, h->st, h->parity);
+    if (e == hipSuccess) e = batch_copy(h, h->insts_dev, true);
     if (e == hipSuccess && use_graph && (!h->graphs_valid || h->graph_t_end != t_end))
         e = capture_graphs(h, t_end);
     for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
@@ -580,6 +663,7 @@ int gs_batch_advance(gs_batch* h, int nsteps, double t_end, int use_graph)
             e = batch_step(h, h->insts_dev, h->total_items, h->parity, t_end);
         h->parity ^= 1;
     }
+    if (e == hipSuccess) e = batch_copy(h, h->insts_dev, false);
     if (e == hipSuccess) e = hipEventRecord(h->ev_out, h->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->user_stream, h->ev_out, 0);
     return e == hipSuccess ? GS_OK : bhip(h, e, "batch advance");
@@ -645,16 +729,15 @@ int gs_batch_autotune(gs_batch* h, const char* cache_path, int* tile_y, int* chu
         for (void* p : scratch)
             if (p) (void)hipFree(p);
     };
+    // padded scratch copies of the states, filled below through the table
     for (int i = 0; i < h->count; ++i) {
-        const long long ncell = (long long)h->dims[i][0] * h->dims[i][1] * h->dims[i][2];
-        const size_t bytes = (size_t)ncell * NV * h->esize * (h->dtype == GS_F32 ? 2 : 1);
-        if ((e = hipMalloc(&scratch[i], bytes)) != hipSuccess ||
-            (e = hipMemcpyAsync(scratch[i], h->states[i], bytes, hipMemcpyDeviceToDevice, h->stream)) !=
-                hipSuccess) {
+        const size_t bytes = (size_t)state_arrays(h) * padded_field(h, i) * h->esize;
+        if ((e = hipMalloc(&scratch[i], bytes)) != hipSuccess) {
             free_scratch();
             return bhip(h, e, "autotune scratch");
         }
     }
+    bool filled = false;
     const int tiles[2] = {16, 8};
     const int chunks[3] = {16, 32, 64};
     const int saved_ty = h->tile_y, saved_kz = h->chunk_z;
@@ -668,13 +751,19 @@ int gs_batch_autotune(gs_batch* h, const char* cache_path, int* tile_y, int* chu
             h->tile_y = ty;
             h->chunk_z = kz;
             int total = 0;
-            std::vector<BatchInst> t = batch_table(h, scratch, h->tune_st, &total);
+            std::vector<BatchInst> t = batch_table(h, h->states, scratch, h->tune_st, &total);
             e = hipMemcpy(h->tune_dev, t.data(), sizeof(BatchInst) * h->count, hipMemcpyHostToDevice);
             if (e != hipSuccess) break;
+            if (!filled) {
+                e = batch_copy(h, h->tune_dev, true);
+                if (e != hipSuccess) break;
+                filled = true;
+            }
             h->total_items = total;
             batch_grids(h);
             int par = 0;
-            e = batch_rates(h, scratch, h->tune_st, par);
+            // time steps of the caller's states (unchanged by the tuning)
+            e = batch_rates(h, h->states, h->tune_st, par);
             if (e == hipSuccess) e = batch_step(h, h->tune_dev, total, par, 0.0);  // warm-up
             par ^= 1;
             if (e == hipSuccess) e = hipEventRecord(a, h->stream);

@@ -14,14 +14,11 @@
 //     iteration ahead), the left face state of face k+1/2 and the z-flux of
 //     face k-1/2.  Every z-face flux is computed once.
 //   * In the plane, primitives of the tile plus a two-cell halo (a cross: the
-//     stencil never reads corners) are staged in LDS.  Thread (tx, ty) limits
-//     its own cell along x and y once, keeps the right states of its low-side
-//     faces and passes the left states of its high-side faces to the next
-//     cells through the flux buffers; it then computes the x-face to its left
-//     and the y-face below it, and one wave computes the TX + TY faces on the
-//     far edges, so every in-plane slope and face is computed once.  Face
-//     fluxes go to LDS, and the divergence reads the two faces of each cell
-//     back.
+//     stencil never reads corners) are staged in LDS.  Thread (tx, ty)
+//     computes the x-face to its left and the y-face below it; one wave
+//     computes the TX + TY faces on the far edges, so every in-plane face is
+//     also computed once.  Face fluxes go to LDS, and the divergence reads the
+//     two faces of each cell back.
 //   * Ghost cells are virtual: every index outside the mesh is mapped to the
 //     proper cell it copies (outflow) or wraps to (periodic) before loading,
 //     so arrays hold proper cells only and GhostExchange costs no pass.
@@ -47,7 +44,7 @@
 namespace gs {
 
 template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE, bool NTH>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T>::waves)))
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T, TY>::waves)))
 stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom g, PhysT<T> kt,
              Phys kd, DevState* __restrict__ st, int parity, double dt_host, double t_end,
              double* __restrict__ dt_log, int step)
@@ -251,6 +248,8 @@ struct gs_fluid {
     int tile_y, chunk_z;   // launch shape (0 = default)
     std::string err;
     bool profile;
+    bool rate_ready;       // rate[parity] holds the max signal rate of the
+                           // state the last step or advance wrote
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[K_COUNT];
 };
@@ -322,6 +321,7 @@ Launch make_launch(const gs_fluid* h)
     g.ny = h->ny;
     g.nz = h->nz;
     g.periodic = (h->bc == GS_BC_PERIODIC);
+    g.pitch = h->nx;
     g.plane = h->nx * h->ny;
     g.field = (long long)h->nx * h->ny * h->nz;
     g.ntx = (h->nx + L.tx - 1) / L.tx;
@@ -538,14 +538,16 @@ StepArrays<T> step_arrays(gs_fluid* h, T* u)
     return a;
 }
 
+// One step of size dt; rate: the second substep also accumulates the max
+// signal rate of U(n+1) into the next parity's slot.
 template <typename T>
-hipError_t step_t(gs_fluid* h, T* u, double dt)
+hipError_t step_t(gs_fluid* h, T* u, double dt, bool rate)
 {
     StepArrays<T> a = step_arrays(h, u);
     hipError_t e = launch_stage<T>(h, 1, false, false, u, u, a.u1, nullptr, a.d0, dt, 0.0,
                                    nullptr, 0);
     if (e == hipSuccess)
-        e = launch_stage<T>(h, 2, false, false, a.u1, u, u, a.comp, a.d0, dt, 0.0, nullptr, 0);
+        e = launch_stage<T>(h, 2, false, rate, a.u1, u, u, a.comp, a.d0, dt, 0.0, nullptr, 0);
     return e;
 }
 
@@ -628,6 +630,7 @@ void init_handle(gs_fluid* h, int nx, int ny, int nz, double dx, double dy, doub
     h->tile_y = 0;
     h->chunk_z = 0;
     h->profile = false;
+    h->rate_ready = false;
 }
 
 // Device address of the allocation-free workspace on each device, looked up
@@ -722,15 +725,47 @@ int gs_fluid_dt(gs_fluid* h, const void* U, double* dt_out)
     return GS_OK;
 }
 
+int gs_fluid_dt_last(gs_fluid* h, double* dt_out)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (!dt_out) return fail(h, GS_ERR_ARG, "dt_out is NULL");
+    if (!h->rate_ready)
+        return fail(h, GS_ERR_STATE, "the last state written was not written by gs_fluid_advance "
+                                     "or gs_fluid_step_dt (or the time was set since)");
+    int r = sync_state(h);
+    if (r != GS_OK) return r;
+    double rate = __builtin_bit_cast(double, h->host_st->rate[h->parity]);
+    if (!(rate > 0.0) || !std::isfinite(rate))
+        return fail(h, GS_ERR_NONPHYSICAL, "signal rate is not positive and finite");
+    *dt_out = h->cfl / rate;
+    return GS_OK;
+}
+
 int gs_fluid_step(gs_fluid* h, void* U, double dt)
 {
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
     if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
     if (!finite_pos(dt)) return fail(h, GS_ERR_ARG, "dt must be finite and > 0");
-    hipError_t e = (h->dtype == GS_F32) ? step_t(h, (float*)U, dt) : step_t(h, (double*)U, dt);
-    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+    hipError_t e = (h->dtype == GS_F32) ? step_t(h, (float*)U, dt, false)
+                                        : step_t(h, (double*)U, dt, false);
     h->parity ^= 1;
+    h->rate_ready = false;
+    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
     return GS_OK;
+}
+
+int gs_fluid_step_dt(gs_fluid* h, void* U, double dt, double* dt_next)
+{
+    if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
+    if (check_state(h, U) != GS_OK) return GS_ERR_ARG;
+    if (!finite_pos(dt)) return fail(h, GS_ERR_ARG, "dt must be finite and > 0");
+    if (!dt_next) return fail(h, GS_ERR_ARG, "dt_next is NULL");
+    hipError_t e = (h->dtype == GS_F32) ? step_t(h, (float*)U, dt, true)
+                                        : step_t(h, (double*)U, dt, true);
+    h->parity ^= 1;
+    h->rate_ready = (e == hipSuccess);
+    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+    return gs_fluid_dt_last(h, dt_next);
 }
 
 int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end, double* dt_log)
@@ -743,6 +778,7 @@ int gs_fluid_advance(gs_fluid* h, void* U, int nsteps, double t_end, double* dt_
     if (nsteps == 0) return GS_OK;
     hipError_t e = (h->dtype == GS_F32) ? advance_t(h, (float*)U, nsteps, t_end, dt_log)
                                         : advance_t(h, (double*)U, nsteps, t_end, dt_log);
+    h->rate_ready = (e == hipSuccess);
     if (e != hipSuccess) return hip_fail(h, e, "advance launch");
     return GS_OK;
 }
@@ -829,6 +865,7 @@ int gs_fluid_set_time(gs_fluid* h, double t)
     if (!h) return fail(nullptr, GS_ERR_ARG, "handle is NULL");
     if (!std::isfinite(t)) return fail(h, GS_ERR_ARG, "t must be finite");
     hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(1), 0, h->stream, h->st, h->parity, t);
+    h->rate_ready = false;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GS_OK : hip_fail(h, e, "set_time");
 }

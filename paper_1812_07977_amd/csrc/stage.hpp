@@ -19,8 +19,9 @@ namespace gs {
 struct Geom {
     int nx, ny, nz;
     int periodic;
-    int plane;          // nx * ny
-    long long field;    // nx * ny * nz: distance between fields
+    int pitch;          // distance between rows (>= nx)
+    int plane;          // pitch * ny: distance between planes
+    long long field;    // pitch * ny * nz: distance between fields
     int ntx, nty;       // tiles along x, y
     int kz, nchunk;     // planes per chunk, chunks along z
     int band;           // tiles per XCD band (0: plain block order)
@@ -105,16 +106,13 @@ __device__ __forceinline__ void load5_nt(const T* __restrict__ base, long long f
 // RATE: accumulate the max signal rate of Uout into rate[parity ^ 1].
 // Primitive recovery and signal rates run in FP64 for both forms (kd); the
 // reconstruction and flux arithmetic runs in T (kt).
-#ifndef GS_STAGE_WAVES_PER_EU
-#define GS_STAGE_WAVES_PER_EU 2
-#endif
-#ifndef GS_STAGE_WAVES_PER_EU_F32
-#define GS_STAGE_WAVES_PER_EU_F32 3
-#endif
-
-template <typename T>
+// Waves per SIMD of the stage kernels: three for both forms (the FP64 body
+// fits 168 VGPRs without spills; with two, the SIMD idles while its waves
+// wait on LDS and memory), except FP64 32 x 8 tiles, whose LDS (57 KiB per
+// workgroup) admits two workgroups per CU.
+template <typename T, int TY>
 struct StageOcc {
-    static constexpr int waves = sizeof(T) == 8 ? GS_STAGE_WAVES_PER_EU : GS_STAGE_WAVES_PER_EU_F32;
+    static constexpr int waves = (sizeof(T) == 8 && TY == 8) ? 2 : 3;
 };
 
 // FP64 constants for the FP64 parts: the FP64 form's own constants, or the
@@ -153,7 +151,7 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
     // own column (ghost columns of ragged tiles map to valid cells)
     const int i = x0 + tx, j = y0 + ty;
     const bool active = (i < g.nx) & (j < g.ny);
-    const int own = map_index(j, g.ny, g.periodic) * g.nx + map_index(i, g.nx, g.periodic);
+    const int own = map_index(j, g.ny, g.periodic) * g.pitch + map_index(i, g.nx, g.periodic);
 
     // halo role: 4 cells per tile row (x) and per tile column (y).  Halo
     // thread h loads its cell of plane z+3 in the iteration of plane z, at
@@ -176,19 +174,7 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         halo = true;
     }
     if (halo)
-        hoff = map_index(y0 + hyl, g.ny, g.periodic) * g.nx + map_index(x0 + hxl, g.nx, g.periodic);
-
-    constexpr int PLW = WY * WX;               // one field of Ws
-    constexpr int PFX = TY * (TX + 1), PFY = (TY + 1) * TX;
-
-    // low-side halo role: the halo threads of the cells just left of the
-    // tile (x = -1) and just below it (y = -1) limit their cell along that
-    // axis and write the left state of the tile's first face into the flux
-    // buffer slot of face -1/2.
-    const bool hlow = halo && ((hxl == -1) || (hyl == -1));
-    const int h_step = (hxl == -1) ? 1 : WX;
-    T* h_out = (hxl == -1) ? &Fx[0][hyl][0] : &Fy[0][0][hxl];
-    const int h_fs = (hxl == -1) ? PFX : PFY;
+        hoff = map_index(y0 + hyl, g.ny, g.periodic) * g.pitch + map_index(x0 + hxl, g.nx, g.periodic);
 
     // edge-face role: the last TX + TY threads compute the faces on the far
     // edges of the tile, y-faces above row TY-1 (e < TX) and x-faces right of
@@ -198,16 +184,18 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
     // cross-component sum so that this performs the very operations of an
     // x-face evaluation, giving bit-identical fluxes.
     const int e = tid - (NT - (TX + TY));
+    constexpr int PLW = WY * WX;               // one field of Ws
+    constexpr int PFX = TY * (TX + 1), PFY = (TY + 1) * TX;
     int e_base = 0, e_step = 0, e_v1 = PLW, e_v2 = 2 * PLW;
     T* e_out = nullptr;
     int e_f1 = PFY, e_f2 = 2 * PFY, e_fs = PFY;
     if (e >= 0 && e < TX) {
-        e_base = (TY + 1) * WX + e + 2;
+        e_base = TY * WX + e + 2;
         e_step = WX;
         e_out = &Fy[0][TY][e];
     } else if (e >= TX) {
         const int r = e - TX;
-        e_base = (r + 2) * WX + TX + 1;
+        e_base = (r + 2) * WX + TX;
         e_step = 1;
         e_v1 = 2 * PLW;
         e_v2 = PLW;
@@ -217,7 +205,6 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         e_fs = PFX;
     }
 
-    // -dt / h per axis: the update is sum_d (F(+) - F(-)) (-dt / h_d)
     const T dtT = (T)dt;
     const T sx = -dtT * kt.inv_h[0], sy = -dtT * kt.inv_h[1], sz = -dtT * kt.inv_h[2];
 
@@ -277,67 +264,48 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         }
         __syncthreads();
 
-        // in-plane slopes, once per cell and axis: each thread limits its own
-        // cell along x and y, keeps the right states of the faces on its low
-        // sides (i-1/2, j-1/2) in registers and writes the left states of the
-        // faces on its high sides into the flux buffers, where the thread
-        // owning the next cell reads them; the halo threads at x = -1 and
-        // y = -1 do the same for the tile's first faces.
-        T WRx[NV], WRy[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const T c = Wk[v];
-            const T sx = minmod(c - Ws[v][ty + 2][tx + 1], Ws[v][ty + 2][tx + 3] - c);
-            const T sy = minmod(c - Ws[v][ty + 1][tx + 2], Ws[v][ty + 3][tx + 2] - c);
-            WRx[v] = fmaR(T(-0.5), sx, c);
-            WRy[v] = fmaR(T(-0.5), sy, c);
-            Fx[v][ty][tx + 1] = fmaR(T(0.5), sx, c);
-            Fy[v][ty + 1][tx] = fmaR(T(0.5), sy, c);
-        }
-        if (hlow) {
-            const T* p = &Ws[0][hyl + 2][hxl + 2];
+        // in-plane faces: x-face left of the own cell, y-face below it
+        {
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const T c = p[v * PLW];
-                const T s = minmod(c - p[v * PLW - h_step], p[v * PLW + h_step] - c);
-                h_out[v * h_fs] = fmaR(T(0.5), s, c);
+                a[v] = Ws[v][ty + 2][tx];
+                b[v] = Ws[v][ty + 2][tx + 1];
+                c[v] = Ws[v][ty + 2][tx + 2];
+                d[v] = Ws[v][ty + 2][tx + 3];
             }
-        }
-        __syncthreads();
-
-        // x-face left of the own cell, y-face below it
-        {
-            T L[NV], f[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) L[v] = Fx[v][ty][tx];
-            hll_flux<0>(L, WRx, kt, f);
+            face_flux<0>(a, b, c, d, kt, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fx[v][ty][tx] = f[v];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) L[v] = Fy[v][ty][tx];
-            hll_flux<1>(L, WRy, kt, f);
+            for (int v = 0; v < NV; ++v) {
+                a[v] = Ws[v][ty][tx + 2];
+                b[v] = Ws[v][ty + 1][tx + 2];
+                d[v] = Ws[v][ty + 3][tx + 2];
+            }
+            face_flux<1>(a, b, c, d, kt, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fy[v][ty][tx] = f[v];
         }
-        // faces on the far edges of the tile (one evaluation per lane): the
-        // left state waits in the flux buffer, the right state is the limited
-        // halo cell beyond the edge
+        // faces on the far edges of the tile (one evaluation per lane)
         if (e >= 0) {
             const T* ws = &Ws[0][0][0];
             const int off[NV] = {0, e_v1, e_v2, 3 * PLW, 4 * PLW};
-            const int fo[NV] = {0, e_f1, e_f2, 3 * e_fs, 4 * e_fs};
-            T L[NV], Rr[NV], f[NV];
+            T a[NV], b[NV], c[NV], d[NV], f[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const T* p = ws + off[v] + e_base;
-                const T c = p[e_step];
-                const T s = minmod(c - p[0], p[2 * e_step] - c);
-                Rr[v] = fmaR(T(-0.5), s, c);
-                L[v] = e_out[fo[v]];
+                a[v] = p[0];
+                b[v] = p[e_step];
+                c[v] = p[2 * e_step];
+                d[v] = p[3 * e_step];
             }
-            hll_flux<1>(L, Rr, kt, f);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) e_out[fo[v]] = f[v];
+            face_flux<1>(a, b, c, d, kt, f);
+            e_out[0] = f[0];
+            e_out[e_f1] = f[1];
+            e_out[e_f2] = f[2];
+            e_out[3 * e_fs] = f[3];
+            e_out[4 * e_fs] = f[4];
         }
         __syncthreads();
 

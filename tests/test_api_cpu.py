@@ -79,6 +79,8 @@ def test_null_handle_calls_are_argument_errors():
     d = ctypes.c_double()
     n = ctypes.c_int()
     assert L.gs_fluid_dt(None, None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_dt_last(None, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
+    assert L.gs_fluid_step_dt(None, None, 0.1, ctypes.byref(d)) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_step(None, None, 0.1) == lib_mod.GS_ERR_ARG
     assert L.gs_fluid_advance(None, None, 1, 0.0, None) == lib_mod.GS_ERR_ARG
     tot = (ctypes.c_double * 5)()

@@ -30,6 +30,7 @@ def test_bench_line_on_a_small_mesh():
     roof = line["roofline"]
     assert 0 < roof["frac"] < 1 and roof["achieved"] == pytest.approx(roof["frac"] * roof["peak"], rel=1e-3)
     assert line["repeats"]["blocks"] == 5 and line["host_dt"]["steps"] == 20
+    assert line["host_dt_last"]["steps"] == 20 and line["host_dt_last"]["value"] > 0
     ceil = line["hbm_ceiling_gbs"]
     for key in ("copy_1to1", "copy_1to1_nt", "add_2to1", "add_2to1_nt", "torch_copy"):
         assert ceil[key] > 0, key

@@ -32,3 +32,21 @@ def test_advance_to_raises_if_the_end_time_is_never_reached():
     with pytest.raises(RuntimeError):
         learned._advance_to(F, None, 1.0, limit=5)
     assert F.steps == 10
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_input_features_match_the_oracle(mode):
+    # the statistics of the network's inputs are taken on features that the
+    # driver computes in torch; they must be the features the kernels feed
+    # the network (mode 1 is checked against the same oracle function on the
+    # GPU), here against the oracle on a seeded state with large velocities
+    import numpy as np
+    import torch
+
+    import oracle.cnn as ocnn
+    import workloads as wl
+    U = wl.random_plane(12, 10, 8, seed=4, v=(1.5, -0.7, 0.3))
+    got = learned.input_features(torch.from_numpy(U), mode).numpy()
+    want = U if mode == 0 else ocnn.features(U, 1.4)
+    assert got.shape == want.shape
+    assert np.allclose(got, want, rtol=1e-14, atol=1e-14)

@@ -363,6 +363,32 @@ def test_host_dt_and_device_dt_interleave():
     assert np.array_equal(to_cpu(U), ref)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dt_last_equals_a_reduction_of_the_state_written(dtype):
+    # the max fused into a step's second substep gives the time step of the
+    # state it wrote exactly as a reduction pass over that state does
+    from paper_1812_07977_amd import GSError, Fluid
+    _say(f"case: dt_last, {dtype} 40x24x20 random plane outflow, 5 steps")
+    U0 = wl.random_plane(40, 24, 20, seed=2, v=(0.4, -0.2, 0.1))
+    with Fluid((40, 24, 20), bc="outflow", dtype=dtype) as F:
+        S = F.state_from(U0)
+        with pytest.raises(GSError):
+            F.dt_last()                      # nothing stepped yet
+        dt = F.dt(S)
+        for _ in range(5):
+            dt = F.step_dt(S, dt)
+            assert dt == F.dt(S) == F.dt_last()
+        F.advance(S, 3)
+        assert F.dt_last() == F.dt(S)
+        F.step(S, dt)
+        with pytest.raises(GSError):
+            F.dt_last()                      # a plain step takes no max
+        F.advance(S, 1)
+        F.time = 0.0
+        with pytest.raises(GSError):
+            F.dt_last()                      # time reset: no step since
+
+
 def test_two_handles_on_two_streams_match_each_alone():
     # two solvers with their own streams, device words and workspaces, their
     # advances queued concurrently (FP64 and FP32, different meshes), give
