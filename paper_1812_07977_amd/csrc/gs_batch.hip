@@ -195,10 +195,11 @@ __global__ void clear_words_kernel(unsigned int* __restrict__ w, int n)
 
 // Copies every problem's state between the caller's layout (rows of nx
 // cells) and the batch's padded one (rows of g.pitch cells, each row
-// starting on a 128-byte line), one wave per row: IN copies caller ->
-// padded, else padded -> caller.  arrays = fields of a state (5; the FP32
-// form's pair 10).  Workgroup (p, s) walks rows s, s + gridDim.y, ... of
-// problem p; the padding cells are never read by the stage kernels.
+// starting on a 128-byte line): IN copies caller -> padded, else padded ->
+// caller.  arrays = fields of a state (5; the FP32 form's pair 10).
+// Workgroup (p, s) takes planes s, s + gridDim.y, ... of problem p (a plane
+// is one field at one z), one wave per row; the padding cells are never
+// read by the stage kernels.
 template <typename T, bool IN>
 __global__ void __launch_bounds__(256)
 copy_rows_kernel(const BatchInst* __restrict__ insts, int arrays)
@@ -206,21 +207,18 @@ copy_rows_kernel(const BatchInst* __restrict__ insts, int arrays)
     const BatchInst& I = insts[blockIdx.x];
     if (I.U == I.Uc) return;  // steps run on the caller's state itself
     const int nx = I.g.nx, ny = I.g.ny, nz = I.g.nz;
-    const long long rows = (long long)arrays * nz * ny;
-    const long long dense_field = (long long)nx * ny * nz;
     T* pad = global_ptr<T>(I.U);
     T* den = global_ptr<T>(I.Uc);
-    const int lane = threadIdx.x & 63;
-    for (long long r = (long long)blockIdx.y * 4 + (threadIdx.x >> 6); r < rows;
-         r += (long long)gridDim.y * 4) {
-        const long long a = r / ((long long)nz * ny);
-        const long long kj = r - a * nz * ny;
-        const long long k = kj / ny, j = kj - k * ny;
-        T* d = den + a * dense_field + (k * ny + j) * nx;
-        T* q = pad + a * I.g.field + k * I.g.plane + j * I.g.pitch;
-        for (int i = lane; i < nx; i += 64) {
-            if (IN) q[i] = d[i];
-            else d[i] = q[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int pl = blockIdx.y; pl < arrays * nz; pl += gridDim.y) {
+        const int a = pl / nz, k = pl - a * nz;
+        T* d = den + ((long long)a * nz + k) * ny * nx;
+        T* q = pad + (long long)a * I.g.field + (long long)k * I.g.plane;
+        for (int j = wave; j < ny; j += 4) {
+            for (int i = lane; i < nx; i += 64) {
+                if (IN) q[(long long)j * I.g.pitch + i] = d[(long long)j * nx + i];
+                else d[(long long)j * nx + i] = q[(long long)j * I.g.pitch + i];
+            }
         }
     }
 }
