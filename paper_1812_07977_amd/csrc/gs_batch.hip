@@ -163,12 +163,16 @@ batch_stage_kernel(const BatchInst* __restrict__ insts, int count, int total, in
         // across it
         int ltid = tid;
         asm volatile("" : "+v"(ltid));
+        // FP64: the streams touched once carry the non-temporal hint (2%
+        // faster over the 64-problem batch); FP32: no hint (with it the
+        // FP32 batch ran 35% slower)
+        constexpr bool NTH = sizeof(T) == 8;
         if (STAGE == 1)
-            stage_tile<T, TX, TY, 1, false, false>(U, U, U1, nullptr, D0, g, kt, K, tix, tiy, kc, dt,
-                                                   bad, rmax, ltid);
+            stage_tile<T, TX, TY, 1, false, NTH>(U, U, U1, nullptr, D0, g, kt, K, tix, tiy, kc, dt,
+                                                 bad, rmax, ltid);
         else
-            stage_tile<T, TX, TY, 2, RATE, false>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad,
-                                                  rmax, ltid);
+            stage_tile<T, TX, TY, 2, RATE, NTH>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad,
+                                                rmax, ltid);
         if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
         if (RATE) {
             for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));

@@ -76,6 +76,15 @@ __device__ __forceinline__ u16 f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((unsigned)b << 16); }
 
+// compensated accumulation (Knuth's TwoSum): s + c tracks the exact sum
+// of the added values to about one FP64 rounding of the total
+__device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
+{
+    double t = s + x, bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
 __device__ __forceinline__ int wrap_or_clamp(int i, int n, int periodic)
 {
     if (periodic) {
@@ -250,6 +259,90 @@ __device__ __forceinline__ void stage_store(u32x4* __restrict__ plane,
     }
 }
 
+// ---------------------------------------------------------------------------
+// state of the correction, and its reductions
+// ---------------------------------------------------------------------------
+
+struct CorrState {
+    double mean[NF];      // channel means of y
+    double moved[NF];     // total represented change per field
+    double mag[NF];       // sum of |change| per field
+    unsigned int bad;     // a corrected cell is non-physical
+    int applied, fallbacks;
+    int ok;               // decision of the last correction
+};
+
+// The mean of each field from n per-block partials partial[b * NF + f]: one
+// wave per field (wave w of the calling workgroup takes fields w, w + waves,
+// ...), TwoSum over the partials lane-strided, then a fixed shuffle tree.
+// Also clears the check's accumulators.
+__device__ __forceinline__ void mean_body(const double* __restrict__ partial, int n, long long ncell,
+                                          CorrState* __restrict__ cs)
+{
+    const int lane = threadIdx.x & 63;
+    for (int f = threadIdx.x >> 6; f < NF; f += blockDim.x >> 6) {
+        double S = 0.0, C = 0.0;
+        for (int b = lane; b < n; b += 64) two_sum_add(S, C, partial[b * NF + f]);
+        for (int off = 32; off > 0; off >>= 1) {
+            double s2 = __shfl_xor(S, off), c2 = __shfl_xor(C, off);
+            two_sum_add(S, C, s2);
+            C += c2;
+        }
+        if (lane == 0) {
+            cs->mean[f] = (S + C) / (double)ncell;
+            cs->moved[f] = 0.0;
+            cs->mag[f] = 0.0;
+        }
+    }
+    if (threadIdx.x == 0) cs->bad = 0u;
+}
+
+// Decision from n per-block partials of the check (moved, magnitude per
+// field): accept unless a candidate cell is non-physical or some |total
+// change| exceeds 1e-5 of the change's magnitude plus 1e-30 (also false for
+// NaN).  Wave w of the calling workgroup takes fields w, w + waves, ...,
+// and sums their partials in a fixed order; every thread of the workgroup
+// must call it.
+__device__ __forceinline__ void decide_body(const double* __restrict__ partial, int n,
+                                            CorrState* __restrict__ cs)
+{
+    __shared__ int okf[NF];
+    const int lane = threadIdx.x & 63;
+    for (int f = threadIdx.x >> 6; f < NF; f += blockDim.x >> 6) {
+        double moved = 0.0, mag = 0.0;
+        for (int b = lane; b < n; b += 64) {
+            moved += partial[b * 2 * NF + 2 * f];
+            mag += partial[b * 2 * NF + 2 * f + 1];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            moved += __shfl_xor(moved, off);
+            mag += __shfl_xor(mag, off);
+        }
+        if (lane == 0) {
+            cs->moved[f] = moved;
+            cs->mag[f] = mag;
+            okf[f] = (fabs(moved) <= 1e-5 * mag + 1e-30) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = cs->bad == 0u;
+        for (int g = 0; g < NF; ++g) ok = ok && okf[g];
+        cs->ok = ok ? 1 : 0;
+        if (ok)
+            cs->applied += 1;
+        else
+            cs->fallbacks += 1;
+    }
+}
+
+// Where the last convolution of a correction sums its outputs for the mean
+// removal (mode 0); part == nullptr in every other launch.
+struct MeanSums {
+    double* part;     // [workgroup][NF] sums of the stored outputs
+    double clip;      // > 0: values are clamped to [-clip, clip] before summing
+};
+
 // X: CL input with CINP channels.  Wp: fragment-packed weights.  Output per
 // EPI: RELU_BF16 -> CL BF16 [v][16 NB] of max(acc + bias, 0); F32_SOA ->
 // FP32 [co][v] for co < cout_valid, acc + bias; MASK_BF16 -> CL BF16 of acc
@@ -269,14 +362,25 @@ __device__ __forceinline__ void stage_store(u32x4* __restrict__ plane,
 template <int CINP, int NB, int EPI>
 __global__ void __launch_bounds__(CONV_THREADS)
 conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* __restrict__ bias,
-            void* __restrict__ out, const u16* __restrict__ mask, ConvGeom g, int cout_valid)
+            void* __restrict__ out, const u16* __restrict__ mask, ConvGeom g, int cout_valid,
+            MeanSums ms_out)
 {
     using S = Stage<CINP>;
     constexpr int KB = (CINP == 32) ? TAPS : 7;
     constexpr int COUT = 16 * NB;
-    __shared__ u32x4 Wl[KB * NB * 64];
+    // one N-block of 32-channel inputs (the last layer): each lane keeps its
+    // 27 weight fragments in registers, so the products read only their A
+    // fragments from LDS; otherwise the fragments are staged in LDS
+    constexpr bool WREG = CINP == 32 && NB == 1;
+    __shared__ u32x4 Wl[WREG ? 1 : KB * NB * 64];
     __shared__ u32x4 In[RING * S::PLANE];
-    for (int i = threadIdx.x; i < KB * NB * 64; i += CONV_THREADS) Wl[i] = ((const u32x4*)Wp)[i];
+    u32x4 wr[WREG ? TAPS : 1];
+    if constexpr (WREG) {
+#pragma unroll
+        for (int t = 0; t < TAPS; ++t) wr[t] = ((const u32x4*)Wp)[t * 64 + (threadIdx.x & 63)];
+    } else {
+        for (int i = threadIdx.x; i < KB * NB * 64; i += CONV_THREADS) Wl[i] = ((const u32x4*)Wp)[i];
+    }
 
     constexpr int RW = CONV_ROWS;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -300,6 +404,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
     float bv[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) bv[nb] = (EPI == EPI_MASK_BF16) ? 0.0f : bias[16 * nb + xl];
+    double msum = 0.0, mcomp = 0.0;  // F32_SOA with ms_out: this lane's sum of channel xl
 
     for (int item = blockIdx.x; item < g.items; item += gridDim.x) {
         const int tile = item % ntile, chunk = item / ntile;
@@ -354,25 +459,30 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                         const u32x4* src = pl[dz] + lane_off + dx;
 #pragma unroll
                         for (int j = 0; j < RW + 2; ++j) fa[cur][j] = src[j * HT];
+                        if constexpr (!WREG) {
 #pragma unroll
-                        for (int dy = 0; dy < 3; ++dy)
+                            for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                            for (int nb = 0; nb < NB; ++nb)
-                                fb[cur][dy][nb] = Wl[((dz * 9 + dy * 3 + dx) * NB + nb) * 64 + l];
+                                for (int nb = 0; nb < NB; ++nb)
+                                    fb[cur][dy][nb] = Wl[((dz * 9 + dy * 3 + dx) * NB + nb) * 64 + l];
+                        }
                     }
                     if (q > 0) {
                         const int prv = (q - 1) & 1;
+                        const int pz = (q - 1) / 3, px = (q - 1) % 3;
 #pragma unroll
                         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                            for (int nb = 0; nb < NB; ++nb)
+                            for (int nb = 0; nb < NB; ++nb) {
+                                const u32x4 b = WREG ? wr[(pz * 9 + dy * 3 + px) % (WREG ? TAPS : 1)]
+                                                     : fb[prv][dy][nb];
 #pragma unroll
-                                for (int r = 0; r < RW; ++r)
-                                    acc[r][nb] = mfma(fa[prv][r + dy], fb[prv][dy][nb], acc[r][nb]);
+                                for (int r = 0; r < RW; ++r) acc[r][nb] = mfma(fa[prv][r + dy], b, acc[r][nb]);
+                            }
                     }
                     if (q > 0 && q < 9) {
                         // issue the next group's reads first, then this group's products
-                        __builtin_amdgcn_sched_group_barrier(0x100, RW + 2 + 3 * NB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, RW + 2 + (WREG ? 0 : 3 * NB), 0);
                         __builtin_amdgcn_sched_group_barrier(0x008, 3 * RW * NB, 0);
                     }
                     __builtin_amdgcn_sched_barrier(0);
@@ -413,6 +523,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                 // when they are all inside the mesh and aligned
                 const int xa = x0 + 4 * grp;
                 const bool vec = (g.nx & 3) == 0 && xa + 3 < g.nx;
+                double pl_sum = 0.0;  // this plane's stored values of channel xl
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
                     const int y = y0 + RW * wave + r;
@@ -427,7 +538,18 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                         for (int i = 0; i < 4; ++i)
                             if (xa + i < g.nx) o[i] = acc[r][0][i] + b0;
                     }
+                    if (ms_out.part) {
+                        // the correction's mean removal: the stored values,
+                        // clipped as the correction clips them
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            double q = (double)(acc[r][0][i] + b0);
+                            if (ms_out.clip > 0.0) q = fmin(fmax(q, -ms_out.clip), ms_out.clip);
+                            pl_sum += (xa + i < g.nx) ? q : 0.0;
+                        }
+                    }
                 }
+                if (ms_out.part) two_sum_add(msum, mcomp, pl_sum);
             } else {
                 const int x = x0 + 4 * grp + q;
 #pragma unroll
@@ -465,6 +587,32 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
         for (int z = z0; z < z1; z += 2) {
             plane(z, pa, pb);
             if (z + 1 < z1) plane(z + 1, pb, pa);
+        }
+    }
+    if constexpr (EPI == EPI_F32_SOA) {
+        if (ms_out.part) {
+            // per-workgroup sums of the NF channels (cout_valid = NF): lanes
+            // xl, xl + 16, xl + 32, xl + 48 of a wave, then the waves in
+            // order
+            __shared__ double wsum[CONV_THREADS / 64][16][2];
+            for (int off = 16; off < 64; off <<= 1) {
+                const double s2 = __shfl_xor(msum, off), c2 = __shfl_xor(mcomp, off);
+                two_sum_add(msum, mcomp, s2);
+                mcomp += c2;
+            }
+            if (l < 16) {
+                wsum[wave][l][0] = msum;
+                wsum[wave][l][1] = mcomp;
+            }
+            __syncthreads();
+            if (threadIdx.x < NF) {
+                double S = 0.0, C = 0.0;
+                for (int w = 0; w < CONV_THREADS / 64; ++w) {
+                    two_sum_add(S, C, wsum[w][threadIdx.x][0]);
+                    C += wsum[w][threadIdx.x][1];
+                }
+                ms_out.part[blockIdx.x * NF + threadIdx.x] = S + C;
+            }
         }
     }
 }
@@ -872,23 +1020,6 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 // correction with fallback
 // ---------------------------------------------------------------------------
 
-struct CorrState {
-    double mean[NF];      // channel means of y
-    double moved[NF];     // total represented change per field
-    double mag[NF];       // sum of |change| per field
-    unsigned int bad;     // a corrected cell is non-physical
-    int applied, fallbacks;
-    int ok;               // decision of the last correction
-};
-
-// TwoSum accumulation of the channel sums of y, one partial pair per block
-__device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
-{
-    double t = s + x, bp = t - s;
-    c += (s - (t - bp)) + (x - bp);
-    s = t;
-}
-
 // the per-field quantity whose mean the correction removes: y (mode 0) or
 // S y (mode 1), S from the head of U; from the cell's values of both
 __device__ __forceinline__ void scaled_from(const float head[NF], const float yv[NF], const Norm& nm,
@@ -955,26 +1086,13 @@ mean_partial_kernel(const float* __restrict__ U, const float* __restrict__ y, lo
     }
 }
 
-// one wave per field: TwoSum over the block partials, lane-strided, then a
-// fixed shuffle tree
+// the mean of y (or S y) from n block partials, as its own one-workgroup
+// launch (five waves)
 __global__ void __launch_bounds__(64 * NF)
 mean_final_kernel(const double* __restrict__ partial, int n, long long ncell,
                   CorrState* __restrict__ cs)
 {
-    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double S = 0.0, C = 0.0;
-    for (int b = lane; b < n; b += 64) two_sum_add(S, C, partial[b * NF + f]);
-    for (int off = 32; off > 0; off >>= 1) {
-        double s2 = __shfl_xor(S, off), c2 = __shfl_xor(C, off);
-        two_sum_add(S, C, s2);
-        C += c2;
-    }
-    if (lane == 0) {
-        cs->mean[f] = (S + C) / (double)ncell;
-        cs->moved[f] = 0.0;
-        cs->mag[f] = 0.0;
-    }
-    if (threadIdx.x == 0) cs->bad = 0u;
+    mean_body(partial, n, ncell, cs);
 }
 
 // The corrected pair of one cell and field: delta = tau (q - mean) rounded
@@ -1037,38 +1155,11 @@ check_kernel(const float* __restrict__ U, const float* __restrict__ y, long long
     if (threadIdx.x < 2 * NF) partial[blockIdx.x * 2 * NF + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// decision: accept unless non-physical, or some |total change| exceeds
-// 1e-5 of the change's magnitude plus 1e-30 (also false for NaN).  One wave
-// per field sums the block partials in a fixed order.
+// the decision from n block partials of check_kernel (five waves)
 __global__ void __launch_bounds__(64 * NF)
 decide_kernel(const double* __restrict__ partial, int n, CorrState* __restrict__ cs)
 {
-    __shared__ int okf[NF];
-    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double moved = 0.0, mag = 0.0;
-    for (int b = lane; b < n; b += 64) {
-        moved += partial[b * 2 * NF + 2 * f];
-        mag += partial[b * 2 * NF + 2 * f + 1];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        moved += __shfl_xor(moved, off);
-        mag += __shfl_xor(mag, off);
-    }
-    if (lane == 0) {
-        cs->moved[f] = moved;
-        cs->mag[f] = mag;
-        okf[f] = (fabs(moved) <= 1e-5 * mag + 1e-30) ? 1 : 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        bool ok = cs->bad == 0u;
-        for (int g = 0; g < NF; ++g) ok = ok && okf[g];
-        cs->ok = ok ? 1 : 0;
-        if (ok)
-            cs->applied += 1;
-        else
-            cs->fallbacks += 1;
-    }
+    decide_body(partial, n, cs);
 }
 
 // If the decision accepted the candidate, write it into U in place: each
@@ -1221,10 +1312,10 @@ int conv_grid(const ConvGeom& g)
 
 template <int CINP, int NB, int EPI>
 void launch_conv(gs_cnn* h, const ConvGeom& g, const u16* X, const u16* Wp, const float* bias, void* out,
-                 const u16* mask, int cout_valid)
+                 const u16* mask, int cout_valid, MeanSums ms = MeanSums{})
 {
     hipLaunchKernelGGL((conv_kernel<CINP, NB, EPI>), dim3(conv_grid<CINP, NB, EPI>(g)), dim3(CONV_THREADS), 0,
-                       h->stream, X, Wp, bias, out, mask, g, cout_valid);
+                       h->stream, X, Wp, bias, out, mask, g, cout_valid, ms);
 }
 
 hipError_t pack_all(gs_cnn* h)
@@ -1245,15 +1336,16 @@ hipError_t pack_all(gs_cnn* h)
     return hipGetLastError();
 }
 
-// forward pass from the head of U; keeps x, h1, h2; writes y
-hipError_t forward(gs_cnn* h, const float* U)
+// forward pass from the head of U; keeps x, h1, h2; writes y (and, with
+// ms.part, the sums of y for the correction's mean removal)
+hipError_t forward(gs_cnn* h, const float* U, MeanSums ms = MeanSums{})
 {
     const ConvGeom g = conv_geom(h);
     hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(h->ncell)), dim3(THREADS), 0, h->stream, U,
                        h->ncell, h->norm, h->x);
     launch_conv<8, 2, EPI_RELU_BF16>(h, g, h->x, h->wf1, h->P + B1_OFF, h->h1, nullptr, HID);
     launch_conv<32, 2, EPI_RELU_BF16>(h, g, h->h1, h->wf2, h->P + B2_OFF, h->h2, nullptr, HID);
-    launch_conv<32, 1, EPI_F32_SOA>(h, g, h->h2, h->wf3, h->P + B3_OFF, h->y, nullptr, NF);
+    launch_conv<32, 1, EPI_F32_SOA>(h, g, h->h2, h->wf3, h->P + B3_OFF, h->y, nullptr, NF, ms);
     return hipGetLastError();
 }
 
@@ -1553,7 +1645,16 @@ int gs_cnn_correct(gs_cnn* h, void* U)
     if (!h) return cfail(nullptr, GS_ERR_ARG, "handle is NULL");
     if (!U || !aligned16(U)) return cfail(h, GS_ERR_ARG, "U is NULL or not 16-byte aligned");
     const long long n = h->ncell;
-    hipError_t e = forward(h, (const float*)U);
+    // mode 0: the last convolution also sums its outputs per workgroup (no
+    // separate pass over y)
+    const int g3 = conv_grid<32, 1, EPI_F32_SOA>(conv_geom(h));
+    const bool fused_mean = h->norm.mode == 0 && g3 <= 2 * RED_BLOCKS;
+    MeanSums ms{};
+    if (fused_mean) {
+        ms.part = h->red;
+        ms.clip = h->norm.clip;
+    }
+    hipError_t e = forward(h, (const float*)U, ms);
     if (e != hipSuccess) return chip(h, e, "correct: forward");
     gs::Phys k;
     k.gamma = h->gamma;
@@ -1561,10 +1662,11 @@ int gs_cnn_correct(gs_cnn* h, void* U)
     k.inv_gm1 = 1.0 / (h->gamma - 1.0);
     for (int d = 0; d < 3; ++d) k.inv_h[d] = 1.0;
     k.cfl = 1.0;
-    hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream,
-                       (const float*)U, h->y, n, h->norm, h->red);
-    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, n,
-                       h->cs);
+    if (!fused_mean)
+        hipLaunchKernelGGL(mean_partial_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream,
+                           (const float*)U, h->y, n, h->norm, h->red);
+    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red,
+                       fused_mean ? g3 : RED_BLOCKS, n, h->cs);
     hipLaunchKernelGGL(check_kernel, dim3(RED_BLOCKS), dim3(THREADS), 0, h->stream, (const float*)U,
                        h->y, n, h->norm, k, h->cs, h->red, h->cs);
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64 * NF), 0, h->stream, h->red, RED_BLOCKS, h->cs);
