@@ -490,6 +490,46 @@ def test_committed_correction_is_the_kahan_sum_of_the_delta():
     assert not np.array_equal(after, before)
 
 
+@pytest.mark.parametrize("shape, clip", [((48, 20, 9), 0.0), ((70, 37, 40), 0.05)])
+def test_committed_correction_with_clip_is_the_kahan_sum_of_the_delta(shape, clip):
+    # mode 0 sums the network output for the mean inside the last
+    # convolution: on a ragged mesh of several work items per workgroup, with
+    # and without clipping, the committed state is still the Kahan sum of
+    # tau (clip(y) - mean clip(y)) with y from the plain forward pass
+    import math
+    import torch
+    import workloads as wl
+    from paper_1812_07977_amd import Fluid
+    from paper_1812_07977_amd.learned import init_params
+    nx, ny, nz = shape
+    U0 = wl.random_plane(nx, ny, nz, seed=23, v=(0.1, 0.3, -0.2))
+    with Fluid(shape, bc="outflow", dtype="f32") as F:
+        S = F.state_from(U0)
+        torch.cuda.synchronize()
+    tau = np.array([1e-3, 2e-3, 2e-3, 2e-3, 4e-3])
+    with _net(shape, bc="outflow") as N:
+        N.set_params(init_params(31, out_scale=1.0))
+        N.set_norm(U0.mean(axis=(1, 2, 3)), U0.std(axis=(1, 2, 3)) + 1e-3, tau)
+        N.set_features(0, clip)
+        y = N.forward(S).cpu().numpy().astype(np.float64)
+        before = S.cpu().numpy()
+        N.correct(S)
+        assert N.counts() == (1, 0)
+        after = S.cpu().numpy()
+    if clip > 0:
+        assert np.mean(np.abs(y) > clip) > 0.05  # the clip is exercised
+        y = np.clip(y, -clip, clip)
+    head, comp = before[0], before[1]
+    for f in range(5):
+        mean = math.fsum(y[f].ravel()) / y[f].size
+        d = (tau[f] * (y[f] - mean)).astype(np.float32)
+        yy = d - comp[f]
+        s = head[f] + yy
+        c2 = (s - head[f]) - yy
+        assert np.array_equal(after[0][f], s), f
+        assert np.array_equal(after[1][f], c2), f
+
+
 def test_scale_aware_targets_and_clipped_correction():
     import torch
     import workloads as wl
