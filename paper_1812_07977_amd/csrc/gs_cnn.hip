@@ -350,13 +350,16 @@ struct MeanSums {
 //
 // Persistent: workgroup b takes work items b, b + grid, ...; an item is one
 // 16 x 16 tile over kz consecutive planes.  Eight waves (two per SIMD, so
-// one's products overlap the other's stores and waits) share the weights
-// and the ring; wave w computes rows 2w, 2w+1 of the tile (two M-blocks of
-// 16 cells) for all NB N-blocks, reading its operand fragments from LDS one
+// one's products overlap the other's stores and waits) share the ring; in
+// general wave w computes rows 2w, 2w+1 of the tile (two M-blocks of 16
+// cells) for all NB N-blocks, reading its operand fragments from LDS one
 // group ahead of the products that use them: for 32 input channels a group
 // is the three taps (dz, 0..2, dx), whose A fragments are four rows (the
 // same rows shifted by dy); for 8 input channels a group is one K-block of
-// four taps.  The next plane of the ring
+// four taps.  The forward hidden layer (32 -> 32) instead gives wave w rows
+// 4 (w % 4) .. 4 (w % 4) + 3 and N-block w / 4, with that block's weights
+// in registers (six A fragments per group, no B reads); the last layer
+// (one N-block) keeps its weights in registers too.  The next plane of the ring
 // is fetched into registers before the products of the current plane and
 // written to LDS after them.
 template <int CINP, int NB, int EPI>
@@ -371,25 +374,36 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
     // one N-block of 32-channel inputs (the last layer): each lane keeps its
     // 27 weight fragments in registers, so the products read only their A
     // fragments from LDS; otherwise the fragments are staged in LDS
-    constexpr bool WREG = CINP == 32 && NB == 1;
+    // Two N-blocks of 32-channel inputs (the hidden layer): the eight waves
+    // split the tile as four groups of four rows times the two N-blocks, and
+    // each lane keeps the 27 weight fragments of its N-block in registers,
+    // so each product group reads six A fragments and no B fragment from LDS
+    // (against ten reads per twelve products with two rows and both N-blocks
+    // per wave).
+    constexpr bool SPLIT = CINP == 32 && NB == 2 && EPI == EPI_RELU_BF16;
+    constexpr bool WREG = CINP == 32 && (NB == 1 || SPLIT);
+    constexpr int NBW = SPLIT ? 1 : NB;  // N-blocks per wave
+    const int nb0 = SPLIT ? (int)(threadIdx.x >> 8) : 0;  // the wave's first N-block
     __shared__ u32x4 Wl[WREG ? 1 : KB * NB * 64];
     __shared__ u32x4 In[RING * S::PLANE];
     u32x4 wr[WREG ? TAPS : 1];
     if constexpr (WREG) {
 #pragma unroll
-        for (int t = 0; t < TAPS; ++t) wr[t] = ((const u32x4*)Wp)[t * 64 + (threadIdx.x & 63)];
+        for (int t = 0; t < TAPS; ++t) wr[t] = ((const u32x4*)Wp)[(t * NB + nb0) * 64 + (threadIdx.x & 63)];
     } else {
         for (int i = threadIdx.x; i < KB * NB * 64; i += CONV_THREADS) Wl[i] = ((const u32x4*)Wp)[i];
     }
 
-    constexpr int RW = CONV_ROWS;
+    constexpr int RW = SPLIT ? 4 : CONV_ROWS;  // tile rows per wave
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int rowg = SPLIT ? (wave & 3) : wave;  // the wave's rows: RW rowg ..
+    static_assert((SPLIT ? 4 : CONV_THREADS / 64) * RW == 16, "the waves cover the 16 tile rows");
     const int xl = l & 15, grp = l >> 4;
     const int ntile = g.ntx * g.nty;
     const long long ncell = (long long)g.nx * g.ny * g.nz;
     // per-lane LDS slot of its A fragment for halo offset (0, 0): row RW wave
     // (+ r + dy), column xl (+ dx), chunk grp
-    const int lane_off = (RW * wave) * HT + xl + ((CINP == 32) ? grp * S::CP : 0);
+    const int lane_off = (RW * rowg) * HT + xl + ((CINP == 32) ? grp * S::CP : 0);
     // CINP = 8: K-block kb covers taps 4 kb .. 4 kb + 3, one per lane group
     int kb_plane[KB], kb_off[KB];
     if (CINP != 32) {
@@ -401,9 +415,9 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
             kb_off[kb] = ((tap / 3) % 3) * HT + tap % 3;
         }
     }
-    float bv[NB];
+    float bv[NBW];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) bv[nb] = (EPI == EPI_MASK_BF16) ? 0.0f : bias[16 * nb + xl];
+    for (int nb = 0; nb < NBW; ++nb) bv[nb] = (EPI == EPI_MASK_BF16) ? 0.0f : bias[16 * (nb0 + nb) + xl];
     double msum = 0.0, mcomp = 0.0;  // F32_SOA with ms_out: this lane's sum of channel xl
 
     for (int item = blockIdx.x; item < g.items; item += gridDim.x) {
@@ -429,12 +443,12 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
             // after the quad transpose of the epilogue, lane (grp, xl) holds
             // channels 16 nb + cq .. + 3 of cell x0 + 4 grp + q of each row
             const int q = xl & 3, cq = xl & ~3;
-            uint2 mk[RW][NB];
+            uint2 mk[RW][NBW];
             if (EPI == EPI_MASK_BF16) {
                 const int x = min(x0 + 4 * grp + q, g.nx - 1);
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
-                    const int y = min(y0 + RW * wave + r, g.ny - 1);
+                    const int y = min(y0 + RW * rowg + r, g.ny - 1);
                     const long long v = ((long long)z * g.ny + y) * g.nx + x;
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
@@ -444,12 +458,30 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
             const u32x4* pl[3] = {In + sb * S::PLANE, In + ((sb + 1) & 3) * S::PLANE,
                                   In + ((sb + 2) & 3) * S::PLANE};
 
-            f32x4 acc[RW][NB];
+            f32x4 acc[RW][NBW];
 #pragma unroll
             for (int r = 0; r < RW; ++r)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[r][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (CINP == 32) {
+                for (int nb = 0; nb < NBW; ++nb) acc[r][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (SPLIT) {
+                // group q = (dz, dx): rows 0 .. RW+1 of A; the B fragments of
+                // taps (dz, 0..2, dx) are in registers.  One buffer of A
+                // fragments, its reads scheduled by the compiler (the other
+                // wave of the SIMD covers their latency)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const int dz = q / 3, dx = q % 3;
+                    const u32x4* src = pl[dz] + lane_off + dx;
+                    u32x4 fa[RW + 2];
+#pragma unroll
+                    for (int j = 0; j < RW + 2; ++j) fa[j] = src[j * HT];
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int r = 0; r < RW; ++r)
+                            acc[r][0] = mfma(fa[r + dy], wr[(dz * 9 + dy * 3 + dx) % (WREG ? TAPS : 1)], acc[r][0]);
+                }
+            } else if (CINP == 32) {
                 // group q = (dz, dx): rows 0 .. RW+1 of A, B of taps (dz, 0..2, dx)
                 u32x4 fa[2][RW + 2], fb[2][3][NB];
 #pragma unroll
@@ -473,7 +505,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
 #pragma unroll
                         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                            for (int nb = 0; nb < NB; ++nb) {
+                            for (int nb = 0; nb < NBW; ++nb) {
                                 const u32x4 b = WREG ? wr[(pz * 9 + dy * 3 + px) % (WREG ? TAPS : 1)]
                                                      : fb[prv][dy][nb];
 #pragma unroll
@@ -483,7 +515,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                     if (q > 0 && q < 9) {
                         // issue the next group's reads first, then this group's products
                         __builtin_amdgcn_sched_group_barrier(0x100, RW + 2 + (WREG ? 0 : 3 * NB), 0);
-                        __builtin_amdgcn_sched_group_barrier(0x008, 3 * RW * NB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 3 * RW * NBW, 0);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -526,7 +558,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                 double pl_sum = 0.0;  // this plane's stored values of channel xl
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
-                    const int y = y0 + RW * wave + r;
+                    const int y = y0 + RW * rowg + r;
                     if (y >= g.ny || xl >= cout_valid) continue;
                     float* o = (float*)out + xl * ncell + ((long long)z * g.ny + y) * g.nx + xa;
                     const float b0 = bv[0];
@@ -554,10 +586,10 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                 const int x = x0 + 4 * grp + q;
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
-                    const int y = y0 + RW * wave + r;
+                    const int y = y0 + RW * rowg + r;
                     const long long v = ((long long)z * g.ny + y) * g.nx + x;
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
+                    for (int nb = 0; nb < NBW; ++nb) {
                         float t[4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
@@ -577,7 +609,7 @@ conv_kernel(const u16* __restrict__ X, const u16* __restrict__ Wp, const float* 
                             w.x &= lo0 | hi0;
                             w.y &= lo1 | hi1;
                         }
-                        if (x < g.nx && y < g.ny) *(uint2*)((u16*)out + v * COUT + 16 * nb + cq) = w;
+                        if (x < g.nx && y < g.ny) *(uint2*)((u16*)out + v * COUT + 16 * (nb0 + nb) + cq) = w;
                     }
                 }
             }
