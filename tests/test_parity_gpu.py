@@ -42,6 +42,7 @@ def _assert_parity(gpu, ref, tol=TOL, what=""):
 def _assert_dts(gdt, odt, tol=DT_TOL):
     assert len(gdt) == len(odt)
     rel = np.abs(np.asarray(gdt) - np.asarray(odt)) / np.abs(np.asarray(odt))
+    _say(f"dt: max relative difference {float(np.max(rel)):.3e} over {len(rel)} steps (bound {tol:g})")
     assert np.all(rel <= tol), rel
 
 
@@ -79,7 +80,7 @@ def test_periodic_64_matches_oracle(case):
     U0 = wl.sine_wave(n, n, n) if case == "sine" else wl.random_plane(n, n, n, seed=int(case[-1]))
     ref, odt = oracle_run(U0, "periodic", steps)
     out, gdt, _ = gpu_run_device_dt(U0, "periodic", steps)
-    _assert_dts(gdt, odt, tol=1e-13)
+    _assert_dts(gdt, odt)
     _assert_parity(out, ref)
 
 
@@ -150,7 +151,11 @@ def test_aligned_sod_to_end_time_matches_oracle(axis):
     out, gdt, t = gpu_run_device_dt(U0, "outflow", len(odt) + 3, t_end=0.1)
     # steps after the end time are exact no-ops (dt = 0)
     assert np.all(gdt[len(odt):] == 0.0)
-    _assert_dts(gdt[:len(odt)], odt, tol=1e-13)
+    # the last step is clipped to the end time: its dt is the end time minus
+    # the accumulated time, a difference of nearly equal numbers, so it is
+    # compared in absolute terms (a few units in the last place of t_end)
+    _assert_dts(gdt[:len(odt) - 1], odt[:-1])
+    assert abs(gdt[len(odt) - 1] - odt[-1]) <= 1e-15
     assert t == pytest.approx(0.1, abs=1e-15)
     _assert_parity(out, ref)
 
