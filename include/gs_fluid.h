@@ -86,7 +86,8 @@ enum {
 };
 
 /*
- * Create a solver for an nx*ny*nz mesh of proper cells with widths dx, dy,
+ * Create a solver for an nx*ny*nz mesh of proper cells (nx*ny at most 2^29,
+ * nx*ny*nz*5 at most 2^40) with widths dx, dy,
  * dz, ratio of specific heats gamma (> 1), Courant number cfl (0 < cfl <= 1)
  * and boundary kind bc, on the current HIP device, for states of type dtype
  * (GS_F64 or GS_F32).  stream is a hipStream_t or NULL.  Allocates the

@@ -575,9 +575,11 @@ int check_problem(int nx, int ny, int nz, double dx, double dy, double dz, doubl
                   double cfl, int bc, int dtype)
 {
     if (nx < 1 || ny < 1 || nz < 1) return fail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
-    if ((long long)nx * ny > (1LL << 30) ||
+    // a plane of at most 2^29 cells: the FP64 kernels address a field plane
+    // with 32-bit byte offsets
+    if ((long long)nx * ny > (1LL << 29) ||
         (long long)nx * ny * nz * NV > (1LL << 40))
-        return fail(nullptr, GS_ERR_ARG, "mesh too large");
+        return fail(nullptr, GS_ERR_ARG, "mesh too large (nx*ny at most 2^29 cells)");
     if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
         return fail(nullptr, GS_ERR_ARG, "cell widths must be finite and > 0");
     if (!std::isfinite(gamma) || !(gamma > 1.0))
