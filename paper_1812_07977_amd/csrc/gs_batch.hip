@@ -171,8 +171,8 @@ batch_stage_kernel(const BatchInst* __restrict__ insts, int count, int total, in
             stage_tile<T, TX, TY, 1, false, NTH>(U, U, U1, nullptr, D0, g, kt, K, tix, tiy, kc, dt,
                                                  bad, rmax, ltid);
         else
-            stage_tile<T, TX, TY, 2, RATE, NTH>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad,
-                                                rmax, ltid);
+            stage_tile<T, TX, TY, 2, RATE, NTH, false>(U1, U, U, C, D0, g, kt, K, tix, tiy, kc, dt, bad,
+                                                       rmax, ltid);
         if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
         if (RATE) {
             for (int off = 32; off > 0; off >>= 1) rmax = __builtin_fmax(rmax, __shfl_xor(rmax, off));
