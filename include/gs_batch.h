@@ -33,7 +33,7 @@ typedef struct gs_batch gs_batch;
 
 /*
  * A batch of count problems: dims is a host array [count][3] of (nx, ny, nz)
- * (each >= 1, (nx+15)*ny at most 2^29), states a host array of count device
+ * (each >= 1, (nx+15)*ny below 2^29), states a host array of count device
  * pointers (aligned to 16
  * bytes).  Allocates, per problem, a workspace (one state of the dtype, FP32:
  * with the first increment) and the per-problem device words; for FP64, where

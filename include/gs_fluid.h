@@ -86,7 +86,7 @@ enum {
 };
 
 /*
- * Create a solver for an nx*ny*nz mesh of proper cells (nx*ny at most 2^29,
+ * Create a solver for an nx*ny*nz mesh of proper cells (nx*ny below 2^29,
  * nx*ny*nz*5 at most 2^40) with widths dx, dy,
  * dz, ratio of specific heats gamma (> 1), Courant number cfl (0 < cfl <= 1)
  * and boundary kind bc, on the current HIP device, for states of type dtype

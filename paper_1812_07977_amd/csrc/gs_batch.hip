@@ -553,10 +553,11 @@ int gs_batch_create(int count, const int* dims, double gamma, double cfl, int bc
     for (int i = 0; i < count; ++i) {
         const int nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
         if (nx < 1 || ny < 1 || nz < 1) return bfail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
-        // a plane of at most 2^29 cells, rows padded to 16 included: the FP64
-        // kernels address a field plane with 32-bit byte offsets
-        if ((long long)(nx + 15) * ny > (1LL << 29))
-            return bfail(nullptr, GS_ERR_ARG, "mesh too large ((nx+15)*ny at most 2^29 cells)");
+        // a plane of fewer than 2^29 cells, rows padded to 16 included: the
+        // FP64 kernels address a field plane through a buffer resource, whose
+        // range is at most 2^32 - 1 bytes
+        if ((long long)(nx + 15) * ny >= (1LL << 29))
+            return bfail(nullptr, GS_ERR_ARG, "mesh too large ((nx+15)*ny below 2^29 cells)");
         if (!states[i] || ((uintptr_t)states[i] & 15u))
             return bfail(nullptr, GS_ERR_ARG, "a state pointer is NULL or not 16-byte aligned");
         cells += (long long)nx * ny * nz;

@@ -575,11 +575,12 @@ int check_problem(int nx, int ny, int nz, double dx, double dy, double dz, doubl
                   double cfl, int bc, int dtype)
 {
     if (nx < 1 || ny < 1 || nz < 1) return fail(nullptr, GS_ERR_ARG, "mesh sizes must be >= 1");
-    // a plane of at most 2^29 cells: the FP64 kernels address a field plane
-    // with 32-bit byte offsets
-    if ((long long)nx * ny > (1LL << 29) ||
+    // a plane of fewer than 2^29 cells: the FP64 kernels address a field
+    // plane through a buffer resource, whose range is at most 2^32 - 1 bytes,
+    // so the last cell must end below byte 2^32
+    if ((long long)nx * ny >= (1LL << 29) ||
         (long long)nx * ny * nz * NV > (1LL << 40))
-        return fail(nullptr, GS_ERR_ARG, "mesh too large (nx*ny at most 2^29 cells)");
+        return fail(nullptr, GS_ERR_ARG, "mesh too large (nx*ny below 2^29 cells)");
     if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
         return fail(nullptr, GS_ERR_ARG, "cell widths must be finite and > 0");
     if (!std::isfinite(gamma) || !(gamma > 1.0))

@@ -78,8 +78,9 @@ __device__ __forceinline__ void block_tile(const Geom& g, int& tx0, int& ty0, in
 // its 32-bit byte offset, so a load or store costs no per-lane 64-bit
 // address arithmetic (5% of the FP64 loop's VALU instructions, 0.4% of the
 // step's time).  The FP32 form keeps global addressing, which measured
-// faster for it (its batched form 2% so).  A field plane must span fewer
-// than 2^32 bytes.  NT: the non-temporal hint.
+// faster for it (its batched form 2% so).  A buffer resource covers at most
+// 2^32 - 1 bytes, so a field plane must end below byte 2^32 (the create
+// calls accept planes of fewer than 2^29 cells).  NT: the non-temporal hint.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p)

@@ -61,6 +61,7 @@ def _create(**over):
     dict(bc=2), dict(bc=-1), dict(dtype=2), dict(dtype=-1),
     dict(nx=1 << 16, ny=1 << 16, nz=2),
     dict(nx=1 << 15, ny=(1 << 14) + 1, nz=1),  # a plane of more than 2^29 cells
+    dict(nx=1 << 15, ny=1 << 14, nz=1),        # exactly 2^29: its last cell ends at byte 2^32
 ])
 def test_create_rejects_bad_arguments(over):
     st, h = _create(**over)
@@ -192,6 +193,7 @@ def _batch_create(count=2, dims=((8, 8, 8), (4, 6, 5)), gamma=1.4, cfl=0.5, bc=0
     dict(gamma=1.0), dict(gamma=math.nan), dict(cfl=0.0), dict(cfl=1.01),
     dict(bc=3), dict(dtype=5),
     dict(dims=((8, 8, 8), ((1 << 15) - 14, 1 << 14, 1))),  # padded plane over 2^29 cells
+    dict(dims=((8, 8, 8), ((1 << 15) - 15, 1 << 14, 1))),  # padded plane of exactly 2^29 cells
 ])
 def test_batch_create_rejects_bad_arguments(over):
     st, h = _batch_create(**over)
