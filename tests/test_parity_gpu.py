@@ -291,17 +291,19 @@ def test_full_512_sampled_windows_match_oracle(case):
             assert np.max(np.abs(g[f] - win[f])) / s <= TOL, (o, f)
 
 
-def test_largest_plane_matches_the_tiled_small_mesh():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_largest_plane_matches_the_tiled_small_mesh(dtype):
     # The create call accepts planes of fewer than 2^29 cells: the FP64
     # kernels address a field plane through a buffer resource, whose range
     # ends at byte 2^32 - 1.  This mesh has planes of 2^29 - 1 = 233 x 1103 x
-    # 2089 cells (256999 x 2089), so the last cell of a plane starts at byte
-    # 2^32 - 16.  A periodic state that repeats one 233 x 2089 x 2 block
+    # 2089 cells (256999 x 2089), so the last cell of an FP64 plane starts at
+    # byte 2^32 - 16.  A periodic state that repeats one 233 x 2089 x 2 block
     # along x gives, cell for cell and bit for bit, that block's own result
     # on its 233 x 2089 x 2 periodic mesh with the same cell widths (every
     # stencil sees the same values and dt is the same maximum); the small
-    # mesh is checked against the oracle.  About 95 GB of device memory,
-    # compared on the device.
+    # FP64 mesh is checked against the oracle.  The FP32 form (global
+    # addressing) runs the same comparison of its pairs.  About 95 GB of
+    # device memory, compared on the device.
     import torch
     from paper_1812_07977_amd import Fluid
     bx, ny, nz, steps = 233, 2089, 2, 2
@@ -309,27 +311,33 @@ def test_largest_plane_matches_the_tiled_small_mesh():
     NX = bx * reps
     assert NX * ny == (1 << 29) - 1
     h = 1.0 / ny
-    _say(f"case: plane1 block {bx} x {ny} x {nz} tiled to {NX} x {ny} x {nz}, periodic, {steps} steps")
+    _say(f"case: {dtype} plane1 block {bx} x {ny} x {nz} tiled to {NX} x {ny} x {nz}, periodic, {steps} steps")
     U0 = wl.random_plane(bx, ny, nz, seed=1, v=(0.3, -0.2, 0.1))
-    ref, odt = oracle_run(U0, "periodic", steps, spacing=(h, h, h))
+    kw = dict(spacing=(h, h, h), gamma=GAMMA, cfl=CFL, bc="periodic", dtype=dtype)
     small_log = torch.zeros(steps, dtype=torch.float64, device="cuda")
-    with Fluid((bx, ny, nz), spacing=(h, h, h), gamma=GAMMA, cfl=CFL, bc="periodic") as F:
-        S = torch.from_numpy(U0).cuda()
+    with Fluid((bx, ny, nz), **kw) as F:
+        S = F.state_from(U0)
         F.advance(S, steps, 0.0, small_log)
         F.sync()
-    _assert_dts(small_log.cpu().numpy(), odt)
-    _assert_parity(S.cpu().numpy(), ref)
+    if dtype == "f64":
+        ref, odt = oracle_run(U0, "periodic", steps, spacing=(h, h, h))
+        _assert_dts(small_log.cpu().numpy(), odt)
+        _assert_parity(S.cpu().numpy(), ref)
     big_log = torch.zeros(steps, dtype=torch.float64, device="cuda")
-    B = torch.from_numpy(U0).cuda().repeat(1, 1, 1, reps).contiguous()
+    with Fluid((bx, ny, nz), **kw) as F:
+        B = F.state_from(U0)
+    reps_shape = (1,) * (B.dim() - 1) + (reps,)
+    B = B.repeat(*reps_shape).contiguous()
     try:
-        with Fluid((NX, ny, nz), spacing=(h, h, h), gamma=GAMMA, cfl=CFL, bc="periodic") as F:
+        with Fluid((NX, ny, nz), **kw) as F:
             F.advance(B, steps, 0.0, big_log)
             F.sync()
         assert torch.equal(big_log, small_log)
-        tiles = B.view(5, nz, ny, reps, bx)
-        assert torch.eq(tiles, S.view(5, nz, ny, 1, bx)).all().item()
+        lead = tuple(B.shape[:-1])
+        tiles = B.view(*lead, reps, bx)
+        assert torch.eq(tiles, S.view(*lead, 1, bx)).all().item()
         # the highest offsets of the plane, separately
-        assert torch.equal(B[:, :, :, -bx:], S)
+        assert torch.equal(B[..., -bx:], S)
     finally:
         del B
         torch.cuda.empty_cache()
