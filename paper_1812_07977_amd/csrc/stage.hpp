@@ -299,7 +299,7 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         // prefetch plane z+3 of the own column at the top of the plane, so
         // that it has the whole plane to arrive before the queue rotation
         // at its end consumes it (measured 1% faster than issuing it after
-        // the in-plane faces; 160 / 162 VGPRs in FP64, three waves)
+        // the in-plane faces, still three waves per SIMD)
         T Uk3[NV];
         load5(plane_ptr(Uin, z + 3), F, own, Uk3);
         // stage the plane's primitives in LDS
