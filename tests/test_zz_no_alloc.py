@@ -71,6 +71,15 @@ def test_two_calls_in_a_row_match_the_handle_path(dtype):
     _one_case(U0, small, PERIODIC, dtype, 5, 0.0, 0.004)
 
 
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_largest_mesh_that_fits_the_workspace(dtype):
+    # 136^3 = 2,515,456 cells: 40 B per cell of the 2,516,582-cell workspace,
+    # nearly all of it; periodic, so every ghost mapping wraps
+    shape = (136, 136, 136)
+    assert 136 ** 3 <= 2516582
+    _one_case(wl.random_plane(*shape, seed=11, v=(0.2, 0.1, -0.3)), shape, PERIODIC, dtype, 3, 0.0, 0.0)
+
+
 def test_nonphysical_flag_and_the_next_call():
     import torch
     shape = (12, 10, 8)
