@@ -231,3 +231,30 @@ def test_batch_of_one_matches_the_oracle():
     ref, dts = oracle_run(probs[0], "outflow", 10)
     assert max(rel_linf(got, ref)) <= 1e-12
     assert abs(times[0] - float(np.sum(dts))) <= 1e-14 * 10 * float(np.sum(dts))
+
+
+def test_the_largest_count_of_small_problems():
+    # 65536 problems, the most a batch takes, each 1..4 cells per side
+    # (one-cell and two-cell dimensions included), periodic, against the
+    # oracle problem by problem: the instance table, its binary search and
+    # the XCD shares of the work items at their largest
+    from paper_1812_07977_amd.batch import Batch
+    count, n = 1 << 16, 2
+    rng = np.random.default_rng(4242)
+    dims = [tuple(int(v) for v in rng.integers(1, 5, 3)) for _ in range(count)]
+    probs = [wl.random_plane(nx, ny, nz, seed=10000 + i, v=(0.2, -0.1, 0.3))
+             for i, (nx, ny, nz) in enumerate(dims)]
+    _say(f"case: batch of {count} problems of 1..4 cells per side, periodic, {n} steps")
+    states = [to_gpu(U0) for U0 in probs]
+    with Batch(dims, states, bc="periodic") as B:
+        B.advance(n)
+        times = B.times()
+        got = [to_cpu(S) for S in states]
+    worst = 0.0
+    for i, U0 in enumerate(probs):
+        ref, dts = oracle_run(U0, "periodic", n)
+        e = max(rel_linf(got[i], ref))
+        worst = max(worst, e)
+        assert e <= 1e-12, (i, dims[i], e)
+        assert abs(times[i] - float(np.sum(dts))) <= 1e-14 * n * float(np.sum(dts)), i
+    _say(f"largest relative L-infinity difference {worst:.2e}")
