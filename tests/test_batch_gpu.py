@@ -118,6 +118,27 @@ def test_time_clipping_per_problem():
         assert np.array_equal(a, b)
 
 
+def test_zero_steps_change_nothing():
+    from paper_1812_07977_amd.batch import Batch
+    probs = _problems(DIMS[:3], seed0=550)
+    states = [to_gpu(U0) for U0 in probs]
+    with Batch(DIMS[:3], states, bc="periodic") as B:
+        B.advance(0)
+        B.sync()
+        assert B.times() == [0.0, 0.0, 0.0]
+        for S, U0 in zip(states, probs):
+            assert np.array_equal(to_cpu(S), U0)
+        B.advance(2)
+        ta = B.times()
+        after = [to_cpu(S) for S in states]
+    others = [to_gpu(U0) for U0 in probs]
+    with Batch(DIMS[:3], others, bc="periodic") as C:
+        C.advance(2)
+        assert C.times() == ta
+        for a, S in zip(after, others):
+            assert np.array_equal(a, to_cpu(S))
+
+
 def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     from paper_1812_07977_amd.batch import Batch
     probs = _problems(DIMS, seed0=600)

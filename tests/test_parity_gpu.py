@@ -238,6 +238,34 @@ def test_time_set_and_read():
         assert F.time == 0.375
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_zero_steps_change_nothing(dtype):
+    import torch
+    from paper_1812_07977_amd import Fluid
+    shape = (19, 13, 11)
+    U0 = wl.random_plane(*shape, seed=21)
+    _say(f"case: zero-step advance {dtype} {shape} outflow")
+    with Fluid(shape, bc="outflow", dtype=dtype) as F:
+        U = F.state_from(U0)
+        before = U.clone()
+        F.time = 0.125
+        F.advance(U, 0)
+        F.sync()
+        assert torch.equal(U, before)
+        assert F.time == 0.125
+        # the call left the handle as it was: two steps now equal two steps
+        # on a fresh handle from the same state and time
+        F.advance(U, 2)
+        ta = F.time
+    with Fluid(shape, bc="outflow", dtype=dtype) as G:
+        V = G.state_from(U0)
+        G.time = 0.125
+        G.advance(V, 2)
+        tb = G.time
+    assert torch.equal(U, V)
+    assert ta == tb
+
+
 def test_profiling_counts_launches():
     from paper_1812_07977_amd import Fluid
     U = to_gpu(wl.sine_wave(32, 32, 32))

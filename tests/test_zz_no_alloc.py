@@ -80,6 +80,26 @@ def test_largest_mesh_that_fits_the_workspace(dtype):
     _one_case(wl.random_plane(*shape, seed=11, v=(0.2, 0.1, -0.3)), shape, PERIODIC, dtype, 3, 0.0, 0.0)
 
 
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_zero_steps_report_t0_and_leave_the_state(dtype):
+    import torch
+    shape = (14, 9, 7)
+    U0 = wl.random_plane(*shape, seed=8)
+    _say(f"case: noalloc zero steps, dtype {dtype}, {shape}")
+    with Fluid(shape, bc="outflow", dtype="f32" if dtype == F32 else "f64") as F:
+        U = F.state_from(U0)
+    before = U.clone()
+    log = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    t = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    flags = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    _noalloc(U, shape, OUTFLOW, dtype, 0, 0.375, 0.0, log, t, flags)
+    torch.cuda.synchronize()
+    assert torch.equal(U, before)
+    assert t.item() == 0.375
+    assert flags.item() == 0
+    assert log.item() == -1.0        # no step, no dt written
+
+
 def test_nonphysical_flag_and_the_next_call():
     import torch
     shape = (12, 10, 8)
