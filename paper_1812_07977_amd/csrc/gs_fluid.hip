@@ -43,7 +43,7 @@
 
 namespace gs {
 
-template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE, bool NTH>
+template <typename T, int TX, int TY, int STAGE, bool DEVDT, bool RATE, bool NTH, bool FULL>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(StageOcc<T, TY>::waves)))
 stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom g, PhysT<T> kt,
              Phys kd, DevState* __restrict__ st, int parity, double dt_host, double t_end,
@@ -72,8 +72,11 @@ stage_kernel(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn, T* D0, Geom
 
     bool bad = false;
     double rmax = 0.0;
-    stage_tile<T, TX, TY, STAGE, RATE, NTH>(Uin, Un, Uout, Cn, D0, g, kt, K, tix, tiy, kc, dt, bad,
-                                            rmax, tid);
+    // U(n) of the FP64 second substep: issued before the plane's second
+    // barrier in the kernels for ragged tiles, after it in the FULL kernels
+    // (each measured faster where it is used: 2% and 1%)
+    stage_tile<T, TX, TY, STAGE, RATE, NTH, !FULL, FULL>(Uin, Un, Uout, Cn, D0, g, kt, K, tix, tiy,
+                                                         kc, dt, bad, rmax, tid);
 
     // epilogue: flags and the max signal rate, one atomic per wavefront
     if (__any(bad) && (tid & 63) == 0) atomicOr(&st->flags, 1u);
@@ -396,16 +399,23 @@ hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, b
     // non-temporal hints on meshes whose state does not stay in the
     // last-level cache between the substeps
     const bool nth = (double)NV * L.g.field * sizeof(T) >= 128.0 * 1024 * 1024;
+    // whole tiles: every lane of every tile owns a cell of the mesh, and the
+    // FULL kernels apply (bitwise identical; at 512^3 the FP64 step 1.2%
+    // faster, the FP32 step 1%)
+    const bool full = h->nx % TX == 0 && h->ny % TY == 0;
+#define GS_LAUNCH1(S_, D_, R_, N_, W_)                                                            \
+    hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_, N_, W_>), grid, block, 0, h->stream,  \
+                       Uin, Un, Uout, C, D, L.g, kt, kd, h->st, h->parity, dt_host, t_end,        \
+                       dt_log, step)
 #define GS_LAUNCH(S_, D_, R_)                                                                     \
     do {                                                                                          \
-        if (nth)                                                                                  \
-            hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_, true>), grid, block, 0,       \
-                               h->stream, Uin, Un, Uout, C, D, L.g, kt, kd, h->st, h->parity,     \
-                               dt_host, t_end, dt_log, step);                                     \
-        else                                                                                      \
-            hipLaunchKernelGGL((stage_kernel<T, TX, TY, S_, D_, R_, false>), grid, block, 0,      \
-                               h->stream, Uin, Un, Uout, C, D, L.g, kt, kd, h->st, h->parity,     \
-                               dt_host, t_end, dt_log, step);                                     \
+        if (nth) {                                                                                \
+            if (full) GS_LAUNCH1(S_, D_, R_, true, true);                                         \
+            else GS_LAUNCH1(S_, D_, R_, true, false);                                             \
+        } else {                                                                                  \
+            if (full) GS_LAUNCH1(S_, D_, R_, false, true);                                        \
+            else GS_LAUNCH1(S_, D_, R_, false, false);                                            \
+        }                                                                                         \
     } while (0)
     if (stage == 1) {
         if (devdt) GS_LAUNCH(1, true, false);
@@ -420,6 +430,7 @@ hipError_t launch_stage_t(gs_fluid* h, const Launch& L, int stage, bool devdt, b
         }
     }
 #undef GS_LAUNCH
+#undef GS_LAUNCH1
     return hipGetLastError();
 }
 

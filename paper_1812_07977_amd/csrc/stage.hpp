@@ -169,7 +169,8 @@ __device__ __forceinline__ const Phys& phys64(const PhysT<float>&, const Phys& k
 // read and raises rmax to the largest signal rate written (RATE).  All
 // threads of the workgroup call it together (it synchronises on LDS); tid
 // is the caller's thread index in the workgroup.
-template <typename T, int TX, int TY, int STAGE, bool RATE, bool NTH, bool EARLY_UN = true>
+template <typename T, int TX, int TY, int STAGE, bool RATE, bool NTH, bool EARLY_UN = true,
+          bool FULL = false>
 __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* Un, T* Uout, T* Cn,
                                            T* D0, const Geom& g, const PhysT<T>& kt, const Phys& K,
                                            int tix, int tiy, int kc, double dt, bool& bad,
@@ -192,9 +193,14 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
     const int z0 = kc * g.kz;
     const int z1 = min(z0 + g.kz, g.nz);
 
-    // own column (ghost columns of ragged tiles map to valid cells)
+    // own column (ghost columns of ragged tiles map to valid cells).  FULL:
+    // the caller guarantees whole tiles (nx and ny multiples of TX and TY),
+    // so no lane is inactive and the combine and stores take no branch;
+    // with the branch, the compiler's wait counting merges its two paths
+    // conservatively and waits for the plane's stores to complete at the
+    // end of every plane
     const int i = x0 + tx, j = y0 + ty;
-    const bool active = (i < g.nx) & (j < g.ny);
+    const bool active = FULL || ((i < g.nx) & (j < g.ny));
     const int own = map_index(j, g.ny, g.periodic) * g.pitch + map_index(i, g.nx, g.periodic);
 
     // halo role: 4 cells per tile row (x) and per tile column (y).  Halo
@@ -367,8 +373,9 @@ __device__ __forceinline__ void stage_tile(const T* __restrict__ Uin, const T* U
         // they are in flight while the workgroup waits there (2% faster steps
         // in both forms).  U(n) of the FP32 form and its compensation and
         // first increment stay after the barrier (issued before it, they made
-        // the FP32 batched form 3% slower), and so does U(n) in the batched
-        // kernels (EARLY_UN false), whose item loop leaves no registers for it
+        // the FP32 batched form 3% slower), and so does U(n) with EARLY_UN
+        // false: in the batched kernels, whose item loop leaves no registers
+        // for it, and in the FULL kernels, which measured 1% faster so
         if (halo) load5(plane_ptr(Uin, z + 3), F, hoff, Hk);
         constexpr bool UN_EARLY = STAGE == 2 && sizeof(T) == 8 && EARLY_UN;
         T Uo[NV], Co[NV], Do[NV];

@@ -143,6 +143,17 @@ def test_f32_launch_shapes_give_identical_results(launch):
     assert np.array_equal(base, other)
 
 
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_f32_whole_tile_kernels_match_the_ragged_tile_kernels(bc):
+    # 48 x 32: whole 16 x 16 tiles, ragged 32 x 8 tiles
+    U0 = wl.random_plane(48, 32, 12, seed=17, v=(0.5, -0.3, 0.2))
+    _say(f"case: f32 plane (48,32,12) {bc}, 6 steps, 16x16 whole tiles vs 32x8 ragged")
+    _, adt, _, a = f32_run(U0, bc, 6, launch=(16, 0))
+    _, bdt, _, b = f32_run(U0, bc, 6, launch=(8, 0))
+    assert np.array_equal(adt, bdt)
+    assert np.array_equal(a, b)
+
+
 def test_f32_repeated_runs_are_bitwise_identical():
     U0 = wl.random_plane(48, 48, 48, seed=3)
     _, adt, _, a = f32_run(U0, "periodic", 6)

@@ -134,6 +134,27 @@ def test_launch_shapes_give_identical_results(launch, boost):
     assert np.array_equal(base, out)
 
 
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_whole_tile_kernels_match_the_ragged_tile_kernels(bc):
+    # 48 x 32 is a whole number of 16 x 16 tiles (the kernels without an
+    # inactive-lane branch) but not of 32 x 8 tiles (the kernels with it):
+    # the two launches must agree bit for bit, in both substeps, on both
+    # the device-dt and the host-dt path
+    _say(f"case: random_plane (48,32,12) {bc}, 6 steps, 16x16 whole tiles vs 32x8 ragged")
+    U0 = wl.random_plane(48, 32, 12, seed=17, v=(0.5, -0.3, 0.2))
+    a, adt, ta = gpu_run_device_dt(U0, bc, 6, launch=(16, 0))
+    b, bdt, tb = gpu_run_device_dt(U0, bc, 6, launch=(8, 0))
+    assert np.array_equal(adt, bdt) and ta == tb
+    assert np.array_equal(a, b)
+    c, cdt = gpu_run_host_dt(U0, bc, 6, launch=(16, 0))
+    d, ddt = gpu_run_host_dt(U0, bc, 6, launch=(8, 0))
+    assert np.array_equal(cdt, ddt)
+    assert np.array_equal(c, d)
+    ref, odt = oracle_run(U0, bc, 6)
+    _assert_dts(adt, odt)
+    _assert_parity(a, ref)
+
+
 def test_repeated_runs_are_bitwise_identical():
     _say("case: random_plane 48^3 periodic, 10 steps, twice")
     U0 = wl.random_plane(48, 48, 48, seed=2)
