@@ -102,6 +102,21 @@ def test_ragged_meshes_match_oracle(shape, bc):
 
 
 @pytest.mark.parametrize("bc", ["outflow", "periodic"])
+@pytest.mark.parametrize("shape,launch", [((16, 16, 1), (16, 0)), ((32, 16, 3), (16, 0)),
+                                          ((32, 8, 2), (8, 0)), ((64, 16, 5), (8, 2))])
+def test_small_whole_tile_meshes_match_oracle(shape, launch, bc):
+    # one or two whole tiles and one to five planes: the whole-tile kernels
+    # with every ghost plane and column mapped back into the mesh
+    nx, ny, nz = shape
+    _say(f"case: random_plane {shape} {bc}, 6 steps, device dt, launch {launch}")
+    U0 = wl.random_plane(nx, ny, nz, seed=19, v=(0.3, 0.2, -0.4))
+    ref, odt = oracle_run(U0, bc, 6)
+    out, gdt, _ = gpu_run_device_dt(U0, bc, 6, launch=launch)
+    _assert_dts(gdt, odt)
+    _assert_parity(out, ref)
+
+
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
 @pytest.mark.parametrize("sign", [1, -1])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_supersonic_flow_takes_the_one_sided_hll_branches(axis, sign, bc):
