@@ -184,6 +184,10 @@ __device__ __forceinline__ void hll_flux(const R L[NV], const R Rs[NV], const Ph
 // Flux through the face between cells b and c along axis AX, from the
 // primitives of four consecutive cells a, b, c, d: one-sided differences,
 // minmod slopes of b and c, face states b + sigma_b/2 and c - sigma_c/2.
+// Both slopes involve the middle difference d1, and the median of (x, d1, 0)
+// is x clamped to [min(d1, 0), max(d1, 0)], so the two slopes share those
+// bounds: six min/max per field instead of eight, the same values (each
+// form returns one of its arguments or zero).
 template <int AX, typename R>
 __device__ __forceinline__ void face_flux(const R a[NV], const R b[NV], const R c[NV], const R d[NV],
                                           const PhysT<R>& k, R F[NV])
@@ -192,8 +196,9 @@ __device__ __forceinline__ void face_flux(const R a[NV], const R b[NV], const R 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         R d0 = b[v] - a[v], d1 = c[v] - b[v], d2 = d[v] - c[v];
-        L[v] = fmaR(R(0.5), minmod(d0, d1), b[v]);
-        Rs[v] = fmaR(R(-0.5), minmod(d1, d2), c[v]);
+        R lo = minR(d1, R(0)), hi = maxR(d1, R(0));
+        L[v] = fmaR(R(0.5), minR(maxR(d0, lo), hi), b[v]);     // minmod(d0, d1)
+        Rs[v] = fmaR(R(-0.5), minR(maxR(d2, lo), hi), c[v]);   // minmod(d1, d2)
     }
     hll_flux<AX>(L, Rs, k, F);
 }
