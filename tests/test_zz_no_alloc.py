@@ -72,6 +72,15 @@ def test_two_calls_in_a_row_match_the_handle_path(dtype):
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
+def test_whole_tile_mesh_after_a_ragged_one(dtype):
+    # 32 x 48 is whole for both tile shapes: the kernels without the
+    # inactive-lane branch, on the workspace a ragged mesh used just before
+    _one_case(wl.random_plane(37, 20, 9, seed=23), (37, 20, 9), OUTFLOW, dtype, 3, 0.0, 0.0)
+    _one_case(wl.random_plane(32, 48, 10, seed=24, v=(0.2, -0.4, 0.3)), (32, 48, 10), PERIODIC,
+              dtype, 4, 0.125, 0.0)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
 def test_largest_mesh_that_fits_the_workspace(dtype):
     # 136^3 = 2,515,456 cells: 40 B per cell of the 2,516,582-cell workspace,
     # nearly all of it; periodic, so every ghost mapping wraps
