@@ -35,6 +35,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -249,6 +250,7 @@ struct gs_fluid {
     DevState* host_st;     // pinned host mirror for waiting calls
     int parity;
     int tile_y, chunk_z;   // launch shape (0 = default)
+    int cus;               // compute units of the device (0: unknown)
     std::string err;
     bool profile;
     bool rate_ready;       // rate[parity] holds the max signal rate of the
@@ -346,6 +348,23 @@ Launch make_launch(const gs_fluid* h)
         const int kmax = f32 ? 32 : 64;
         if (kz > kmax) kz = kmax;
         if (kz < 8) kz = 8;
+        // FP64: chunks of at most 48 planes, their number rounded up, by at
+        // most half again, so that the work items are a whole multiple of
+        // the workgroups resident at once (three per CU with 16 x 16 tiles,
+        // two with 32 x 8): no partly filled last generation, and shorter
+        // chunks keep neighbouring tiles closer in z.  At 512^3: 12 chunks
+        // of 43 planes, 0.8% faster steps than 8 of 64 (9 of 57: 0.3%; 16 of
+        // 32: 0.3%), results unchanged (a cell's arithmetic does not depend
+        // on the chunking)
+        if (!f32 && h->cus > 0) {
+            const int resident = h->cus * (L.ty == 8 ? 2 : 3);
+            const int klim = kz < 48 ? kz : 48;
+            int c = (h->nz + klim - 1) / klim;
+            const int m = resident / std::gcd(ntile, resident);
+            const int cr = (c + m - 1) / m * m;
+            if (2 * cr <= 3 * c && (h->nz + cr - 1) / cr >= 8) c = cr;
+            kz = (h->nz + c - 1) / c;
+        }
     }
     if (kz > h->nz) kz = h->nz;
     g.kz = kz;
@@ -645,6 +664,12 @@ void init_handle(gs_fluid* h, int nx, int ny, int nz, double dx, double dy, doub
     h->chunk_z = 0;
     h->profile = false;
     h->rate_ready = false;
+    // for the default z-chunk length; without it the default ignores the
+    // resident workgroup count
+    if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        h->cus = 0;
+        (void)hipGetLastError();
+    }
 }
 
 // Device address of the allocation-free workspace on each device, looked up
